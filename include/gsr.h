@@ -1,0 +1,216 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) differentiable Gaussian rasterizer.
+ *
+ * The paper this library serves (On-the-fly Large-scale 3D Reconstruction
+ * from Multi-Camera Rigs) optimises a set of 3D Gaussians -- position, scale,
+ * rotation, opacity and spherical-harmonic colour -- jointly by gradient steps
+ * through a differentiable renderer (Sec. 3.3, "Optimization"), drawing the
+ * frames of several rig cameras and a window of keyframes per iteration
+ * (Sec. 3.3, "Frequency-based Scheduling").  The renderer is the tile-based
+ * rasterizer of 3D Gaussian Splatting, which the paper inherits without
+ * restating.  This library is that per-iteration hot path: EWA projection,
+ * (view | tile | depth) binning with an LDS radix sort, front-to-back alpha
+ * compositing, the reverse-order adjoint, an L1 photometric loss and a fused
+ * Adam step, for a batch of views of arbitrary resolutions in one launch per
+ * stage.
+ *
+ * Conventions shared by every entry point:
+ *  - Array pointers are DEVICE pointers owned by the caller, unless a comment
+ *    says HOST.  Floating-point arrays are float32, structure-of-arrays,
+ *    C-contiguous, at least 16-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Render, loss and optimiser calls only enqueue work on it: they never
+ *    synchronise, allocate or copy to the host, so a caller may capture them
+ *    in a hipGraph.  gsr_plan, gsr_check, gsr_required_capacity and
+ *    gsr_autotune synchronise.
+ *  - Errors are returned as gsr_status; gsr_last_error() holds a message.
+ *    Invalid arguments are rejected before any work is enqueued.
+ *  - A context is not thread-safe; use one per stream.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsr_ctx gsr_ctx;
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_ERR_INVALID_ARG = -1, /* a pointer, size or option is invalid                    */
+  GSR_ERR_CAPACITY = -2,    /* visible records or tile pairs exceeded the plan's capacity */
+  GSR_ERR_HIP = -3,         /* a HIP runtime call failed                                 */
+  GSR_ERR_UNSUPPORTED = -4, /* a value the library does not handle (e.g. SH degree > 3)  */
+  GSR_ERR_NOT_PLANNED = -5  /* render called before gsr_plan, or with other sizes        */
+} gsr_status;
+
+/* Gaussian parameters (Sec. 3.3 optimises all of them), n Gaussians:
+ *   mean          [3][n]   world position x, y, z
+ *   log_scale     [3][n]   log of the per-axis standard deviation (s = exp)
+ *   quat          [4][n]   rotation (w, x, y, z); normalised inside the
+ *                          renderer, gradient taken through the normalisation;
+ *                          a zero quaternion culls the Gaussian
+ *   opacity_logit [n]      opacity = sigmoid(opacity_logit)
+ *   sh            [K][3][n] colour coefficients, K = (sh_degree+1)^2, real
+ *                          orthonormal SH basis ordered l^2 + l + m; colour =
+ *                          max(0, sum_k sh_k Y_k(d) + 0.5), d the unit vector
+ *                          from the camera centre to the mean.            */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  const float *mean;
+  const float *log_scale;
+  const float *quat;
+  const float *opacity_logit;
+  const float *sh;
+} gsr_gaussians;
+
+/* Pinhole camera, world -> camera x_c = R x_w + t, R row-major, OpenCV axes
+ * (x right, y down, z forward).  Pixel (i, j) has its centre at
+ * (i + 0.5, j + 0.5).  72 bytes; arrays of these are passed to render calls
+ * in DEVICE memory so poses can change between graph replays.            */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} gsr_camera;
+
+typedef struct {
+  int32_t tile_size;        /* 8, 16 or 32 (0 = 16)                                     */
+  int64_t capacity_records; /* visible (view, Gaussian) records; 0 = n_views * n (exact) */
+  int64_t capacity_pairs;   /* (record, tile) pairs; 0 = 8 * n_views * n                 */
+  float bg[3];              /* background colour                                       */
+} gsr_plan_options;
+
+/* Forward outputs, flat over views: view v starts at pixel offset pix_off[v]
+ * (from gsr_plan).  image is planar per view: view v occupies
+ * image[3*pix_off[v] .. 3*pix_off[v+1]) as [3][H_v][W_v].                   */
+typedef struct {
+  float *image;        /* [3 * total_pixels]                                      */
+  float *t_final;      /* [total_pixels] transmittance after the last composite    */
+  uint32_t *last_pos;  /* [total_pixels] one past the last composited position in
+                          the pixel's tile list (0 if none); read by the backward */
+  uint32_t *n_contrib; /* [total_pixels] number of composited Gaussians            */
+} gsr_fwd_out;
+
+/* Parameter gradients, same layouts as gsr_gaussians; every entry is written
+ * (invisible Gaussians get zeros).                                           */
+typedef struct {
+  float *mean, *log_scale, *quat, *opacity_logit, *sh;
+} gsr_grads;
+
+/* Create / destroy a context.  The context owns a few device words (status
+ * flags, counters) allocated here.                                          */
+gsr_status gsr_create(gsr_ctx **out);
+void gsr_destroy(gsr_ctx *ctx);
+
+/* Plan a batch: n_views cameras (HOST array; only width/height and the
+ * intrinsics' image extents are used here), n Gaussians of degree sh_degree.
+ * Fixes the tile grid of every view, the workspace layout and capacities.
+ * Outputs: *workspace_bytes, the size of the caller-allocated DEVICE workspace
+ * each render call needs; pix_off (HOST, n_views + 1 entries) the per-view
+ * pixel offsets.  Synchronises (uploads the per-view tile table).
+ * Errors: INVALID_ARG for n_views < 1, n < 0, a non-positive image size, a
+ * tile size other than 0/8/16/32, or sizes beyond the 32-bit index range;
+ * UNSUPPORTED for sh_degree outside 0..3.                                   */
+gsr_status gsr_plan(gsr_ctx *ctx, const gsr_camera *cams_host, int32_t n_views, int64_t n,
+                    int32_t sh_degree, const gsr_plan_options *opt, size_t *workspace_bytes,
+                    int64_t *pix_off);
+
+/* Forward render of every planned view (the 3DGS image model the paper
+ * renders with, Sec. 3.3): projection, binning, per-tile sort, compositing.
+ * cams: DEVICE array of n_views gsr_camera (same sizes as planned).  The
+ * workspace keeps the binning state that gsr_render_backward and
+ * gsr_debug_binning read; it must not be modified in between.  If the visible
+ * records or pairs exceed the capacity, the kernels skip the excess work and
+ * set a device flag that gsr_check reports as GSR_ERR_CAPACITY.            */
+gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                              int32_t n_views, void *workspace, size_t workspace_bytes,
+                              const gsr_fwd_out *out, void *stream);
+
+/* L1 photometric loss over n_elems image values (all views, channels, pixels):
+ * loss = sum |image - target| / n_elems, written to loss_out (DEVICE, 1
+ * float); dL_dimage[i] = sign(image[i] - target[i]) / n_elems.  Deterministic
+ * (fixed-order reduction).                                                  */
+gsr_status gsr_l1_loss(gsr_ctx *ctx, const float *image, const float *target, int64_t n_elems,
+                       float *loss_out, float *dL_dimage, void *stream);
+
+/* Reverse-order adjoint of gsr_render_forward: from dL/dimage (same layout as
+ * the image) to gradients of every Gaussian parameter.  Reads the forward's
+ * workspace state and the fwd outputs t_final / last_pos.  Overwrites grads
+ * (accumulate = 0) or adds to them (accumulate = 1).  Deterministic: no
+ * floating-point atomics.                                                   */
+gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                               int32_t n_views, void *workspace, size_t workspace_bytes,
+                               const gsr_fwd_out *fwd, const float *dL_dimage,
+                               const gsr_grads *grads, int32_t accumulate, void *stream);
+
+/* Adam hyper-parameters: one learning rate per group, in this order:
+ * mean, log_scale, quat, opacity_logit, sh degree 0 (the first 3n sh
+ * entries), sh higher degrees.                                              */
+typedef struct {
+  float lr[6];
+  float beta1, beta2, eps;
+} gsr_adam_config;
+
+/* Optimizer state in the gsr_grads layout (first and second moments). */
+typedef struct {
+  float *mean, *log_scale, *quat, *opacity_logit, *sh;
+} gsr_adam_moments;
+
+/* One dense Adam step with bias correction over all parameters (the paper's
+ * joint gradient update, Sec. 3.3), in one launch.  params are updated in
+ * place (the gsr_gaussians pointers, cast to writable).  step_dev: DEVICE
+ * int32 step counter, incremented on the device before use, so a captured
+ * graph replays correctly.                                                  */
+gsr_status gsr_adam_step(gsr_ctx *ctx, const gsr_grads *params, const gsr_grads *grads,
+                         const gsr_adam_moments *m, const gsr_adam_moments *v,
+                         const gsr_adam_config *cfg, int32_t *step_dev, int64_t n,
+                         int32_t sh_degree, void *stream);
+
+/* Backward and Adam fused: the per-Gaussian backward applies the Adam update
+ * directly, without writing gradients (grads may be NULL) -- same result as
+ * gsr_render_backward followed by gsr_adam_step with grads zeroed first.    */
+gsr_status gsr_render_backward_adam(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                                    int32_t n_views, void *workspace, size_t workspace_bytes,
+                                    const gsr_fwd_out *fwd, const float *dL_dimage,
+                                    const gsr_grads *params, const gsr_adam_moments *m,
+                                    const gsr_adam_moments *v, const gsr_adam_config *cfg,
+                                    int32_t *step_dev, const gsr_grads *grads_out, void *stream);
+
+/* Export the binning of the last forward for parity checks: keys[M] =
+ * (global tile) << 32 | depth bits, vals[M] = Gaussian index, sorted
+ * ascending by (key, value); tile_csr[T_total + 1] the list offsets.  Buffers
+ * are DEVICE, sized from gsr_required_capacity.                            */
+gsr_status gsr_debug_binning(gsr_ctx *ctx, void *workspace, uint64_t *keys, uint32_t *vals,
+                             uint32_t *tile_csr, void *stream);
+
+/* Synchronise `stream`, then report GSR_ERR_CAPACITY if the last forward ran
+ * out of record or pair capacity, else GSR_OK.                              */
+gsr_status gsr_check(gsr_ctx *ctx, void *workspace, void *stream);
+
+/* Synchronise `stream` and read the record and pair counts the last forward
+ * needed (valid also after a capacity overflow), and the total tile count.  */
+gsr_status gsr_required_capacity(gsr_ctx *ctx, void *workspace, int64_t *records, int64_t *pairs,
+                                 int64_t *tiles, void *stream);
+
+/* Test hook for the per-tile sort: tile lists longer than small_max
+ * (1..256, default 256) leave the 256-entry LDS sort; force_class >= 0 sends
+ * every such list to at least size class force_class (0: 2048-entry LDS sort,
+ * 1: 8192-entry LDS sort, 2: global-memory radix sort), -1 chooses by length.
+ * Results are identical for every setting; this exists so that all sort
+ * paths can be exercised on small inputs.  Errors: INVALID_ARG.           */
+gsr_status gsr_set_sort_routing(gsr_ctx *ctx, uint32_t small_max, int32_t force_class);
+
+const char *gsr_last_error(const gsr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

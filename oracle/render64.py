@@ -146,13 +146,30 @@ def render(scene, cams, bg=(0.0, 0.0, 0.0)):
     return [render_view(arrays, scene.sh_degree, cam, bg=bg, p64=p64) for cam in cams]
 
 
-def render_pixel(scene_arrays, sh_degree, cam, i, j, bg=(0.0, 0.0, 0.0), setup=None):
-    """The definition as a literal loop for the single pixel (i, j)."""
+def render_pixels(scene_arrays, sh_degree, cam, pixels, bg=(0.0, 0.0, 0.0), setup=None):
+    """``render_pixel`` for a list of (i, j) pixels, sharing one setup."""
+    setup = setup if setup is not None else view_setup(scene_arrays, sh_degree, cam)
+    spec, order, _ = setup
+    i0, i1, j0, j1 = (b[order] for b in spec["box"])
+    out = []
+    for (i, j) in pixels:
+        ks = np.nonzero((i0 <= i) & (i <= i1) & (j0 <= j) & (j <= j1))[0]
+        out.append(render_pixel(scene_arrays, sh_degree, cam, i, j, bg=bg, setup=setup, candidates=ks))
+    return out
+
+
+def render_pixel(scene_arrays, sh_degree, cam, i, j, bg=(0.0, 0.0, 0.0), setup=None, candidates=None):
+    """The definition as a literal loop for the single pixel (i, j).
+    ``candidates`` optionally restricts the walk to these positions of the
+    sorted order (those whose box contains the pixel); the box test below
+    still applies."""
     spec, order, pj = setup if setup is not None else view_setup(scene_arrays, sh_degree, cam)
     i0, i1, j0, j1 = spec["box"]
     T, C, count, last, amb = 1.0, np.zeros(3), 0, -1, False
     px, py = i + 0.5, j + 0.5
-    for k, g in enumerate(order):
+    walk = range(len(order)) if candidates is None else candidates
+    for k in walk:
+        g = order[k]
         if not (i0[g] <= i <= i1[g] and j0[g] <= j <= j1[g]):
             continue
         dx = px - pj["mu2"][k][0]

@@ -1,0 +1,100 @@
+// Shared device/host definitions of the rasterizer: camera and per-view
+// tables, workspace pointers, and the constants of the image model.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+// Mirrors gsr_camera (72 bytes).
+struct Cam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t w, h;
+};
+static_assert(sizeof(Cam) == 72, "camera layout");
+
+// Per-view tile table fixed by the plan.
+struct ViewInfo {
+  int32_t w, h;          // image size
+  int32_t tiles_x, tiles_y;
+  uint32_t tile_base;    // first global tile id of the view
+  uint32_t diff_base;    // offset of the view's (tiles_x+1)*(tiles_y+1) difference grid
+  uint32_t pix_off;      // first pixel of the view in the flat outputs
+  uint32_t pad;
+};
+
+// Scalars the kernels exchange through device memory.
+enum Scalar : int {
+  kNumRecords = 0,    // visible (view, Gaussian) records
+  kNumPairs = 1,      // (record, tile) pairs
+  kOverflow = 2,      // nonzero: capacity exceeded; later stages skip their work
+  kQueueMid = 3,      // tiles queued for the 2048-entry LDS sort
+  kQueueBig = 4,      // tiles queued for the 8192-entry LDS sort
+  kQueueHuge = 5,     // tiles queued for the global-memory radix sort
+  kLossTicket = 6,    // loss reduction: blocks done
+  kNumScalars = 16
+};
+
+// Workspace arrays (device pointers into the caller's workspace).
+struct Ws {
+  uint32_t *scalars;        // [kNumScalars]              zeroed per forward
+  int32_t *diff;            // [sum_v (tx+1)(ty+1)]       zeroed per forward
+  uint32_t *tile_cursor;    // [T_tot]                    zeroed per forward
+  uint2 *block_sums;        // [n_blocks] (records, pairs) -> exclusive offsets
+  uint32_t *rec_start;      // [n + 1] first record of each Gaussian
+  float4 *rec_payload;      // [cap_rec][4] raster payload, see RecPayload
+  uint32_t *rec_g;          // [cap_rec] Gaussian index
+  uint32_t *rec_view;       // [cap_rec] view index
+  uint32_t *rec_pairoff;    // [cap_rec] first pair of the record (record-major)
+  uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  uint32_t *rec_zbits;      // [cap_rec] depth bits
+  uint32_t *tile_count;     // [T_tot] list length
+  uint32_t *tile_start;     // [T_tot] list start relative to the view's pair base
+  uint32_t *view_pair_base; // [n_views + 1]
+  uint32_t *queues;         // [3][T_tot] tiles for the larger sorts
+  uint64_t *pairs;          // [cap_pairs] (zbits << 32 | record), bucketed by tile
+  uint64_t *pairs_tmp;      // [cap_pairs] ping-pong buffer of the global sort
+  uint32_t *tile_recs;      // [cap_pairs] sorted record list of every tile
+  float4 *partials;         // [cap_pairs][3] backward partial gradients per pair
+  float4 *g2d;              // [cap_rec][3] per-record reduced gradients
+  float *loss_partials;     // [kLossBlocks]
+};
+
+struct Sizes {
+  int64_t n;
+  int32_t n_views;
+  int32_t sh_k;
+  int32_t ts;
+  uint32_t t_tot;
+  uint32_t cap_rec;
+  uint32_t cap_pairs;
+  uint32_t n_blocks;        // ceil(n / kPreBlock)
+  float bg[3];
+};
+
+constexpr int kPreBlock = 256;     // Gaussians per preprocess workgroup
+constexpr int kLossBlocks = 1024;  // loss reduction partials
+
+// Image-model constants (float32 bit patterns written as hex literals).
+constexpr float kNearZ = 0x1.99999ap-3f;       // 0.2
+constexpr float kDilation = 0x1.333334p-2f;    // 0.3
+constexpr float kSupportK = 0x1.62a4a8p+3f;    // 11.0826 >= 2 ln 255
+constexpr float kClampFov = 0x1.4cccccp+0f;    // 1.3
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLog2e = 0x1.715476p+0f;
+constexpr float kHalfLog2e = 0x1.715476p-1f;   // log2(e) / 2
+
+// Raster payload of one record, four float4:
+//  p0 = (i0, i1, j0, j1)            inclusive pixel box, as floats
+//  p1 = (offx, offy, qa, qb)        mean offset from the box corner; conic
+//  p2 = (qc, opacity, r, g)         in Cholesky form (see raster.hpp)
+//  p3 = (b, -, -, -)
+// offx = mu'_x - i0 - 0.5, so dx = (px - i0) - offx is the centre offset of
+// pixel px, exact up to the rounding of offx.
+
+}  // namespace gsr

@@ -1,0 +1,47 @@
+// Host-side launchers of the rasterizer kernels (one translation unit per
+// stage; the runtime calls these in stream order).
+#pragma once
+
+#include "common.hpp"
+
+namespace gsr {
+
+struct GaussPtrs {
+  const float *mean, *log_scale, *quat, *opacity_logit, *sh;
+};
+
+struct MutPtrs {
+  float *mean, *log_scale, *quat, *opacity_logit, *sh;
+};
+
+struct AdamArgs {
+  MutPtrs p, m, v;
+  float lr[6];
+  float beta1, beta2, eps;
+  int32_t *step;
+};
+
+void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
+void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
+                       const Sizes &sz, int sh_degree, hipStream_t st);
+void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st);
+void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max,
+                 int force_q, hipStream_t st);
+void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
+                       uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st);
+void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
+                       const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);
+void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
+                    const MutPtrs *grads, int accumulate, const AdamArgs *adam, hipStream_t st);
+void launch_adam(const MutPtrs &grads, const AdamArgs &a, int64_t n, int sh_degree, hipStream_t st);
+void launch_step_inc(int32_t *step, hipStream_t st);
+void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
+               uint32_t *ticket, hipStream_t st);
+void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint64_t *keys,
+                          uint32_t *vals, uint32_t *csr, hipStream_t st);
+
+// Grid of the per-tile raster kernels: T_tot rounded up to a multiple of 8
+// (one contiguous run of tiles per XCD).
+inline uint32_t tile_grid(uint32_t t_tot) { return (t_tot + 7u) / 8u * 8u; }
+
+}  // namespace gsr

@@ -1,0 +1,74 @@
+// L1 photometric loss with its gradient, and the binning export used by the
+// parity checks.
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "util.hpp"
+
+namespace gsr {
+
+// loss = sum |img - tgt| / n, dL/dimg = sign(img - tgt) / n.  Per-block
+// partial sums in a fixed order; the last block to finish adds the partials
+// in block order, so the value is deterministic.
+__global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const float *__restrict__ tgt, int64_t n,
+                                            float *__restrict__ loss, float *__restrict__ dl,
+                                            float *__restrict__ partials, uint32_t *__restrict__ ticket) {
+  __shared__ float s_red[4];
+  __shared__ bool s_last;
+  const float inv_n = (float)(1.0 / (double)n);
+  float acc = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float d = img[i] - tgt[i];
+    acc += fabsf(d);
+    dl[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+  }
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (lane_id() == 0) s_red[wave_id()] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    __threadfence();
+    s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();
+    double s = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b)
+      s += (double)__hip_atomic_load(partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *loss = (float)(s / (double)n);
+    *ticket = 0u;
+  }
+}
+
+void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
+               uint32_t *ticket, hipStream_t st) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kLossBlocks));
+  k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, loss, dl, partials, ticket);
+}
+
+// One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian.
+__global__ __launch_bounds__(256) void k_debug_binning(Ws ws, Sizes sz, uint64_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ vals, uint32_t *__restrict__ csr) {
+  const uint32_t tile = blockIdx.x;
+  const uint32_t start = ws.tile_start[tile], n = ws.tile_count[tile];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t rec = ws.tile_recs[start + i];
+    keys[start + i] = ((uint64_t)tile << 32) | ws.rec_zbits[rec];
+    vals[start + i] = ws.rec_g[rec];
+  }
+  if (threadIdx.x == 0) {
+    csr[tile] = start;
+    if (tile == sz.t_tot - 1) csr[sz.t_tot] = start + n;
+  }
+}
+
+void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint64_t *keys, uint32_t *vals,
+                          uint32_t *csr, hipStream_t st) {
+  (void)views;
+  if (sz.t_tot == 0) return;
+  k_debug_binning<<<sz.t_tot, 256, 0, st>>>(ws, sz, keys, vals, csr);
+}
+
+}  // namespace gsr

@@ -1,0 +1,208 @@
+// Preprocess: project every (view, Gaussian) pair, compact the visible ones
+// into records (Gaussian-major), and count the (record, tile) pairs per tile.
+//
+// Two passes over the Gaussians with a scan between them (reduce, then
+// scan, then write), so record indices are deterministic and increase with
+// the Gaussian index within each view -- the tie-break order of the sort.
+// Each thread owns one Gaussian and loops over all views, so its parameters
+// (236 bytes at SH degree 3) are read once per pass for the whole batch.
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "sh.hpp"
+#include "spec.hpp"
+#include "util.hpp"
+
+namespace gsr {
+
+__global__ void k_zero_words(uint32_t *__restrict__ p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+__device__ __forceinline__ uint32_t rect_area(const Proj &P, int ts_shift) {
+  const uint32_t w = (uint32_t)((P.i1 >> ts_shift) - (P.i0 >> ts_shift) + 1);
+  const uint32_t h = (uint32_t)((P.j1 >> ts_shift) - (P.j0 >> ts_shift) + 1);
+  return w * h;
+}
+
+__global__ __launch_bounds__(kPreBlock) void k_pre_count(GaussPtrs gp, const Cam *__restrict__ cams,
+                                                         Ws ws, Sizes sz, int ts_shift) {
+  __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
+  const int64_t g = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  uint32_t recs = 0, pairs = 0;
+  if (g < sz.n) {
+    float m3[3], l3[3], q4[4];
+    load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+    for (int v = 0; v < sz.n_views; ++v) {
+      const Cam c = load_cam(cams, v);
+      Proj P;
+      project_spec(m3, l3, q4, c, P);
+      if (P.visible) {
+        recs += 1;
+        pairs += rect_area(P, ts_shift);
+      }
+    }
+  }
+  uint32_t tr, tp;
+  block_excl_scan<kPreBlock>(recs, s_scan, tr);
+  block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
+  if (threadIdx.x == 0) ws.block_sums[blockIdx.x] = make_uint2(tr, tp);
+}
+
+// One workgroup: exclusive scan of the per-block (records, pairs) totals.
+__global__ __launch_bounds__(1024) void k_scan_blocks(Ws ws, Sizes sz) {
+  __shared__ uint64_t s_a[16], s_b[16];
+  const uint32_t nb = sz.n_blocks;
+  const uint32_t per = (nb + 1023u) / 1024u;
+  const uint32_t lo = min(nb, threadIdx.x * per), hi = min(nb, lo + per);
+  uint64_t sr = 0, sp = 0;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint2 b = ws.block_sums[i];
+    sr += b.x;
+    sp += b.y;
+  }
+  uint64_t tr, tp;
+  uint64_t er = block_excl_scan<1024>(sr, s_a, tr);
+  uint64_t ep = block_excl_scan<1024>(sp, s_b, tp);
+  const bool over = tr > sz.cap_rec || tp > sz.cap_pairs;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint2 b = ws.block_sums[i];
+    ws.block_sums[i] = make_uint2((uint32_t)er, (uint32_t)ep);
+    er += b.x;
+    ep += b.y;
+  }
+  if (threadIdx.x == 0) {
+    ws.scalars[kNumRecords] = (uint32_t)min<uint64_t>(tr, 0xFFFFFFFFull);
+    ws.scalars[kNumPairs] = (uint32_t)min<uint64_t>(tp, 0xFFFFFFFFull);
+    ws.scalars[kOverflow] = over ? 1u : 0u;
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam *__restrict__ cams,
+                                                         const ViewInfo *__restrict__ views, Ws ws,
+                                                         Sizes sz, int ts_shift) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
+  if (ws.scalars[kOverflow]) return;
+  const int64_t g = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  const bool live = g < sz.n;
+  float m3[3], l3[3], q4[4];
+  uint32_t recs = 0, pairs = 0;
+  if (live) {
+    load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+    for (int v = 0; v < sz.n_views; ++v) {
+      const Cam c = load_cam(cams, v);
+      Proj P;
+      project_spec(m3, l3, q4, c, P);
+      if (P.visible) {
+        recs += 1;
+        pairs += rect_area(P, ts_shift);
+      }
+    }
+  }
+  uint32_t tr, tp;
+  const uint2 base = ws.block_sums[blockIdx.x];
+  uint32_t rec = base.x + block_excl_scan<kPreBlock>(recs, s_scan, tr);
+  uint32_t pair = base.y + block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
+  if (!live) return;
+  ws.rec_start[g] = rec;
+  if (g == sz.n - 1) ws.rec_start[sz.n] = rec + recs;
+  if (recs == 0) return;
+
+  float sh[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) sh[k][ch] = gp.sh[((int64_t)k * 3 + ch) * sz.n + g];
+  const float op = 1.0f / (1.0f + expf(-gp.opacity_logit[g]));
+
+  for (int v = 0; v < sz.n_views; ++v) {
+    const Cam c = load_cam(cams, v);
+    Proj P;
+    project_spec(m3, l3, q4, c, P);
+    if (!P.visible) continue;
+    // 2D mean in float64 (the pixel grid is ~2^11 wide, so a float32
+    // projection would be off by up to ~1e-4 px); stored as the offset from
+    // the box corner, which float32 represents to ~1e-7 px.
+    const double xd = ((double)c.R[0] * m3[0] + (double)c.R[1] * m3[1]) + (double)c.R[2] * m3[2] + c.t[0];
+    const double yd = ((double)c.R[3] * m3[0] + (double)c.R[4] * m3[1]) + (double)c.R[5] * m3[2] + c.t[1];
+    const double zd = ((double)c.R[6] * m3[0] + (double)c.R[7] * m3[1]) + (double)c.R[8] * m3[2] + c.t[2];
+    const float offx = (float)((double)c.fx * (xd / zd) + (double)c.cx - (double)P.i0 - 0.5);
+    const float offy = (float)((double)c.fy * (yd / zd) + (double)c.cy - (double)P.j0 - 0.5);
+    // Conic in Cholesky form.  With S = A A^T + 0.3 I:
+    //   d^T S^-1 d = (dx + qb dy)^2 * S_yy / det + dy^2 / S_yy,  qb = -S_xy / S_yy
+    // and det = |a0 x a1|^2 + 0.3 (|a0|^2 + |a1|^2) + 0.09 has no cancellation.
+    const float sxx = P.p0 + kDilation, syy = P.p1 + kDilation;
+    const float sxy = (P.a0[0] * P.a1[0] + P.a0[1] * P.a1[1]) + P.a0[2] * P.a1[2];
+    const float cx_ = P.a0[1] * P.a1[2] - P.a0[2] * P.a1[1];
+    const float cy_ = P.a0[2] * P.a1[0] - P.a0[0] * P.a1[2];
+    const float cz_ = P.a0[0] * P.a1[1] - P.a0[1] * P.a1[0];
+    const float det = (cx_ * cx_ + cy_ * cy_ + cz_ * cz_) + kDilation * (P.p0 + P.p1) + kDilation * kDilation;
+    (void)sxx;
+    const float qa = -kHalfLog2e * (syy / det);
+    const float qb = -sxy / syy;
+    const float qc = -kHalfLog2e / syy;
+    // view-dependent colour
+    const float cxw = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+    const float cyw = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+    const float czw = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+    const float dx = m3[0] - cxw, dy = m3[1] - cyw, dz = m3[2] - czw;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    float Y[16];
+    sh_basis(dx * inv, dy * inv, dz * inv, DEG, Y);
+    float rgb[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float s = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) s += sh[k][ch] * Y[k];
+      rgb[ch] = fmaxf(s, 0.0f);
+    }
+    const ViewInfo vi = views[v];
+    ws.rec_payload[(size_t)rec * 4 + 0] = make_float4((float)P.i0, (float)P.i1, (float)P.j0, (float)P.j1);
+    ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
+    ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
+    ws.rec_payload[(size_t)rec * 4 + 3] = make_float4(rgb[2], 0.0f, 0.0f, 0.0f);
+    const int tx0 = P.i0 >> ts_shift, tx1 = P.i1 >> ts_shift;
+    const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
+    ws.rec_g[rec] = (uint32_t)g;
+    ws.rec_view[rec] = (uint32_t)v;
+    ws.rec_pairoff[rec] = pair;
+    ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+    ws.rec_zbits[rec] = P.zbits;
+    // +1/-1 corners of the tile rectangle in the view's difference grid; a 2D
+    // prefix sum of the grid gives every tile's list length.
+    int32_t *D = ws.diff + vi.diff_base;
+    const int stride = vi.tiles_x + 1;
+    atomicAdd(D + ty0 * stride + tx0, 1);
+    atomicAdd(D + ty0 * stride + tx1 + 1, -1);
+    atomicAdd(D + (ty1 + 1) * stride + tx0, -1);
+    atomicAdd(D + (ty1 + 1) * stride + tx1 + 1, 1);
+    rec += 1;
+    pair += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  }
+}
+
+void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
+                       const Sizes &sz, int sh_degree, hipStream_t st) {
+  const int ts_shift = sz.ts == 8 ? 3 : (sz.ts == 16 ? 4 : 5);
+  if (sz.n_blocks == 0) return;
+  k_pre_count<<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift);
+  k_scan_blocks<<<1, 1024, 0, st>>>(ws, sz);
+  switch (sh_degree) {
+    case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    case 1: k_pre_write<1><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    case 2: k_pre_write<2><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    default: k_pre_write<3><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+  }
+}
+
+void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st) {
+  if (n_words == 0) return;
+  const uint64_t blocks = std::min<uint64_t>((n_words + 255) / 256, 4096);
+  k_zero_words<<<(unsigned)blocks, 256, 0, st>>>(p, n_words);
+}
+
+}  // namespace gsr

@@ -1,0 +1,430 @@
+// Host runtime of the C ABI declared in include/gsr.h: planning, workspace
+// layout, argument validation and the stream-ordered launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsr.h"
+#include "kernels.hpp"
+
+using namespace gsr;
+
+namespace {
+
+struct Layout {
+  size_t scalars, diff, cursor, zero_end;
+  size_t block_sums, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
+  size_t tile_count, tile_start, vbase, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
+  size_t total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct gsr_ctx {
+  std::string err;
+  bool planned = false;
+  int32_t n_views = 0;
+  int64_t n = 0;
+  int32_t sh_degree = 0;
+  std::vector<ViewInfo> views;
+  ViewInfo *views_d = nullptr;
+  size_t views_d_count = 0;
+  Sizes sz{};
+  Layout lay{};
+  float *loss_partials = nullptr;
+  uint32_t *loss_ticket = nullptr;
+  uint32_t sort_small_max = 256;
+  int32_t sort_force_class = -1;
+};
+
+namespace {
+
+gsr_status fail(gsr_ctx *c, gsr_status s, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define GSR_HIP(ctx, call)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, GSR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+Ws make_ws(const gsr_ctx *c, void *base) {
+  char *b = static_cast<char *>(base);
+  const Layout &L = c->lay;
+  Ws w;
+  w.scalars = reinterpret_cast<uint32_t *>(b + L.scalars);
+  w.diff = reinterpret_cast<int32_t *>(b + L.diff);
+  w.tile_cursor = reinterpret_cast<uint32_t *>(b + L.cursor);
+  w.block_sums = reinterpret_cast<uint2 *>(b + L.block_sums);
+  w.rec_start = reinterpret_cast<uint32_t *>(b + L.rec_start);
+  w.rec_payload = reinterpret_cast<float4 *>(b + L.payload);
+  w.rec_g = reinterpret_cast<uint32_t *>(b + L.rec_g);
+  w.rec_view = reinterpret_cast<uint32_t *>(b + L.rec_view);
+  w.rec_pairoff = reinterpret_cast<uint32_t *>(b + L.rec_pairoff);
+  w.rec_rect = reinterpret_cast<uint2 *>(b + L.rec_rect);
+  w.rec_zbits = reinterpret_cast<uint32_t *>(b + L.rec_zbits);
+  w.tile_count = reinterpret_cast<uint32_t *>(b + L.tile_count);
+  w.tile_start = reinterpret_cast<uint32_t *>(b + L.tile_start);
+  w.view_pair_base = reinterpret_cast<uint32_t *>(b + L.vbase);
+  w.queues = reinterpret_cast<uint32_t *>(b + L.queues);
+  w.pairs = reinterpret_cast<uint64_t *>(b + L.pairs);
+  w.pairs_tmp = reinterpret_cast<uint64_t *>(b + L.pairs_tmp);
+  w.tile_recs = reinterpret_cast<uint32_t *>(b + L.tile_recs);
+  w.partials = reinterpret_cast<float4 *>(b + L.partials);
+  w.g2d = reinterpret_cast<float4 *>(b + L.g2d);
+  w.loss_partials = c->loss_partials;
+  return w;
+}
+
+Layout make_layout(const Sizes &s, uint32_t diff_words, int32_t n_views) {
+  Layout L{};
+  size_t o = 0;
+  auto put = [&](size_t &field, size_t bytes) {
+    field = o;
+    o = align_up(o + bytes);
+  };
+  put(L.scalars, kNumScalars * 4);
+  put(L.diff, (size_t)diff_words * 4);
+  put(L.cursor, (size_t)s.t_tot * 4);
+  L.zero_end = o;
+  put(L.block_sums, (size_t)s.n_blocks * 8);
+  put(L.rec_start, (size_t)(s.n + 1) * 4);
+  put(L.payload, (size_t)s.cap_rec * 64);
+  put(L.rec_g, (size_t)s.cap_rec * 4);
+  put(L.rec_view, (size_t)s.cap_rec * 4);
+  put(L.rec_pairoff, (size_t)s.cap_rec * 4);
+  put(L.rec_rect, (size_t)s.cap_rec * 8);
+  put(L.rec_zbits, (size_t)s.cap_rec * 4);
+  put(L.tile_count, (size_t)s.t_tot * 4);
+  put(L.tile_start, (size_t)s.t_tot * 4);
+  put(L.vbase, (size_t)(n_views + 1) * 4);
+  put(L.queues, (size_t)s.t_tot * 12);
+  put(L.pairs, (size_t)s.cap_pairs * 8);
+  put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
+  put(L.tile_recs, (size_t)s.cap_pairs * 4);
+  put(L.partials, (size_t)s.cap_pairs * 48);
+  put(L.g2d, (size_t)s.cap_rec * 48);
+  L.total = o;
+  return L;
+}
+
+gsr_status check_gauss(gsr_ctx *c, const gsr_gaussians *g) {
+  if (!g) return fail(c, GSR_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n != c->n || g->sh_degree != c->sh_degree)
+    return fail(c, GSR_ERR_NOT_PLANNED, "gaussians (n=%lld, degree %d) differ from the plan (n=%lld, degree %d)",
+                (long long)g->n, g->sh_degree, (long long)c->n, c->sh_degree);
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->sh))
+    return fail(c, GSR_ERR_INVALID_ARG, "a Gaussian parameter pointer is NULL");
+  return GSR_OK;
+}
+
+gsr_status check_common(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, void *ws, size_t ws_bytes) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (n_views != c->n_views)
+    return fail(c, GSR_ERR_NOT_PLANNED, "n_views %d differs from the plan (%d)", n_views, c->n_views);
+  if (!cams) return fail(c, GSR_ERR_INVALID_ARG, "cams is NULL");
+  if (!ws) return fail(c, GSR_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < c->lay.total)
+    return fail(c, GSR_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, c->lay.total);
+  return GSR_OK;
+}
+
+GaussPtrs gauss_ptrs(const gsr_gaussians *g) {
+  return GaussPtrs{g->mean, g->log_scale, g->quat, g->opacity_logit, g->sh};
+}
+
+MutPtrs mut_ptrs(const gsr_grads *g) {
+  return MutPtrs{g->mean, g->log_scale, g->quat, g->opacity_logit, g->sh};
+}
+
+MutPtrs mut_ptrs(const gsr_adam_moments *g) {
+  return MutPtrs{g->mean, g->log_scale, g->quat, g->opacity_logit, g->sh};
+}
+
+bool any_null(const MutPtrs &p) { return !p.mean || !p.log_scale || !p.quat || !p.opacity_logit || !p.sh; }
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_create(gsr_ctx **out) {
+  if (!out) return GSR_ERR_INVALID_ARG;
+  *out = nullptr;
+  gsr_ctx *c = new gsr_ctx();
+  if (hipMalloc(&c->loss_partials, kLossBlocks * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->loss_ticket, 256) != hipSuccess || hipMemset(c->loss_ticket, 0, 256) != hipSuccess) {
+    gsr_destroy(c);
+    return GSR_ERR_HIP;
+  }
+  *out = c;
+  return GSR_OK;
+}
+
+void gsr_destroy(gsr_ctx *c) {
+  if (!c) return;
+  if (c->views_d) (void)hipFree(c->views_d);
+  if (c->loss_partials) (void)hipFree(c->loss_partials);
+  if (c->loss_ticket) (void)hipFree(c->loss_ticket);
+  delete c;
+}
+
+gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t n, int32_t sh_degree,
+                    const gsr_plan_options *opt, size_t *ws_bytes, int64_t *pix_off) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  c->planned = false;
+  if (!cams || !ws_bytes || !pix_off) return fail(c, GSR_ERR_INVALID_ARG, "NULL argument to gsr_plan");
+  if (n_views < 1) return fail(c, GSR_ERR_INVALID_ARG, "n_views must be >= 1 (got %d)", n_views);
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, GSR_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (sh_degree < 0 || sh_degree > 3) return fail(c, GSR_ERR_UNSUPPORTED, "SH degree %d not in 0..3", sh_degree);
+  int32_t ts = opt ? opt->tile_size : 0;
+  if (ts == 0) ts = 16;
+  if (ts != 8 && ts != 16 && ts != 32) return fail(c, GSR_ERR_INVALID_ARG, "tile size %d not in {8, 16, 32}", ts);
+  std::vector<ViewInfo> views(n_views);
+  uint64_t tiles = 0, diff = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int w = cams[v].width, h = cams[v].height;
+    if (w <= 0 || h <= 0 || w > 65535 || h > 65535)
+      return fail(c, GSR_ERR_INVALID_ARG, "view %d has image size %dx%d", v, w, h);
+    ViewInfo &vi = views[v];
+    vi.w = w;
+    vi.h = h;
+    vi.tiles_x = (w + ts - 1) / ts;
+    vi.tiles_y = (h + ts - 1) / ts;
+    vi.tile_base = (uint32_t)tiles;
+    vi.diff_base = (uint32_t)diff;
+    vi.pix_off = (uint32_t)pix;
+    vi.pad = 0;
+    pix_off[v] = (int64_t)pix;
+    tiles += (uint64_t)vi.tiles_x * vi.tiles_y;
+    diff += (uint64_t)(vi.tiles_x + 1) * (vi.tiles_y + 1);
+    pix += (uint64_t)w * h;
+  }
+  pix_off[n_views] = (int64_t)pix;
+  if (tiles >= (1ull << 31) || diff >= (1ull << 31) || pix * 3 >= (1ull << 32))
+    return fail(c, GSR_ERR_INVALID_ARG, "batch too large for 32-bit tile/pixel indices");
+  uint64_t cap_rec = opt && opt->capacity_records > 0 ? (uint64_t)opt->capacity_records : (uint64_t)n_views * n;
+  uint64_t cap_pairs = opt && opt->capacity_pairs > 0 ? (uint64_t)opt->capacity_pairs : 8ull * n_views * n;
+  cap_rec = std::min<uint64_t>(std::max<uint64_t>(cap_rec, 1), 0xFFFFFFF0ull);
+  cap_pairs = std::min<uint64_t>(std::max<uint64_t>(cap_pairs, 1), 0xFFFFFFF0ull);
+
+  if (c->views_d_count < (size_t)n_views) {
+    if (c->views_d) (void)hipFree(c->views_d);
+    c->views_d = nullptr;
+    c->views_d_count = 0;
+    GSR_HIP(c, hipMalloc(&c->views_d, sizeof(ViewInfo) * n_views));
+    c->views_d_count = n_views;
+  }
+  GSR_HIP(c, hipMemcpy(c->views_d, views.data(), sizeof(ViewInfo) * n_views, hipMemcpyHostToDevice));
+
+  Sizes s{};
+  s.n = n;
+  s.n_views = n_views;
+  s.sh_k = (sh_degree + 1) * (sh_degree + 1);
+  s.ts = ts;
+  s.t_tot = (uint32_t)tiles;
+  s.cap_rec = (uint32_t)cap_rec;
+  s.cap_pairs = (uint32_t)cap_pairs;
+  s.n_blocks = (uint32_t)((n + kPreBlock - 1) / kPreBlock);
+  for (int k = 0; k < 3; ++k) s.bg[k] = opt ? opt->bg[k] : 0.0f;
+  c->views = views;
+  c->sz = s;
+  c->n_views = n_views;
+  c->n = n;
+  c->sh_degree = sh_degree;
+  c->lay = make_layout(s, (uint32_t)diff, n_views);
+  *ws_bytes = c->lay.total;
+  c->planned = true;
+  return GSR_OK;
+}
+
+gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                              void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, void *stream) {
+  gsr_status st = check_common(c, cams, n_views, ws_base, ws_bytes);
+  if (st != GSR_OK) return st;
+  if ((st = check_gauss(c, g)) != GSR_OK) return st;
+  if (!out || !out->image || !out->t_final || !out->last_pos || !out->n_contrib)
+    return fail(c, GSR_ERR_INVALID_ARG, "forward output pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Ws ws = make_ws(c, ws_base);
+  const Cam *cm = reinterpret_cast<const Cam *>(cams);
+  launch_zero(ws.scalars, (c->lay.zero_end - c->lay.scalars) / 4, s);
+  launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, s);
+  launch_binning(c->views_d, ws, c->sz, s);
+  launch_sort(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
+  launch_raster_fwd(c->views_d, ws, c->sz, out->image, out->t_final, out->last_pos, out->n_contrib, s);
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_l1_loss(gsr_ctx *c, const float *image, const float *target, int64_t n_elems, float *loss_out,
+                       float *dL_dimage, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!image || !target || !loss_out || !dL_dimage) return fail(c, GSR_ERR_INVALID_ARG, "NULL argument to gsr_l1_loss");
+  if (n_elems <= 0) return fail(c, GSR_ERR_INVALID_ARG, "n_elems must be positive");
+  launch_l1(image, target, n_elems, loss_out, dL_dimage, c->loss_partials, c->loss_ticket,
+            static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+static gsr_status backward_common(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                  void *ws_base, size_t ws_bytes, const gsr_fwd_out *fwd, const float *dL) {
+  gsr_status st = check_common(c, cams, n_views, ws_base, ws_bytes);
+  if (st != GSR_OK) return st;
+  if ((st = check_gauss(c, g)) != GSR_OK) return st;
+  if (!fwd || !fwd->t_final || !fwd->last_pos) return fail(c, GSR_ERR_INVALID_ARG, "forward state pointer is NULL");
+  if (!dL) return fail(c, GSR_ERR_INVALID_ARG, "dL_dimage is NULL");
+  return GSR_OK;
+}
+
+gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                               void *ws_base, size_t ws_bytes, const gsr_fwd_out *fwd, const float *dL_dimage,
+                               const gsr_grads *grads, int32_t accumulate, void *stream) {
+  gsr_status st = backward_common(c, g, cams, n_views, ws_base, ws_bytes, fwd, dL_dimage);
+  if (st != GSR_OK) return st;
+  if (!grads) return fail(c, GSR_ERR_INVALID_ARG, "grads is NULL");
+  const MutPtrs gr = mut_ptrs(grads);
+  if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Ws ws = make_ws(c, ws_base);
+  launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
+  launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr,
+                 accumulate ? 1 : 0, nullptr, s);
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+static gsr_status adam_args(gsr_ctx *c, const gsr_grads *params, const gsr_adam_moments *m,
+                            const gsr_adam_moments *v, const gsr_adam_config *cfg, int32_t *step, AdamArgs &a) {
+  if (!params || !m || !v || !cfg || !step) return fail(c, GSR_ERR_INVALID_ARG, "NULL Adam argument");
+  a.p = mut_ptrs(params);
+  a.m = mut_ptrs(m);
+  a.v = mut_ptrs(v);
+  if (c->n > 0 && (any_null(a.p) || any_null(a.m) || any_null(a.v)))
+    return fail(c, GSR_ERR_INVALID_ARG, "a parameter or moment pointer is NULL");
+  for (int k = 0; k < 6; ++k) a.lr[k] = cfg->lr[k];
+  a.beta1 = cfg->beta1;
+  a.beta2 = cfg->beta2;
+  a.eps = cfg->eps;
+  a.step = step;
+  if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps >= 0.f))
+    return fail(c, GSR_ERR_INVALID_ARG, "Adam betas must lie in [0, 1) and eps >= 0");
+  return GSR_OK;
+}
+
+gsr_status gsr_adam_step(gsr_ctx *c, const gsr_grads *params, const gsr_grads *grads, const gsr_adam_moments *m,
+                         const gsr_adam_moments *v, const gsr_adam_config *cfg, int32_t *step_dev, int64_t n,
+                         int32_t sh_degree, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (n < 0) return fail(c, GSR_ERR_INVALID_ARG, "n < 0");
+  if (sh_degree < 0 || sh_degree > 3) return fail(c, GSR_ERR_UNSUPPORTED, "SH degree %d not in 0..3", sh_degree);
+  if (!grads) return fail(c, GSR_ERR_INVALID_ARG, "grads is NULL");
+  const int64_t keep_n = c->n;
+  c->n = n;  // pointer checks below use the step's own n
+  AdamArgs a{};
+  gsr_status st = adam_args(c, params, m, v, cfg, step_dev, a);
+  const MutPtrs gr = mut_ptrs(grads);
+  if (st == GSR_OK && n > 0 && any_null(gr)) st = fail(c, GSR_ERR_INVALID_ARG, "a gradient pointer is NULL");
+  c->n = keep_n;
+  if (st != GSR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_step_inc(step_dev, s);
+  launch_adam(gr, a, n, sh_degree, s);
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                    void *ws_base, size_t ws_bytes, const gsr_fwd_out *fwd, const float *dL_dimage,
+                                    const gsr_grads *params, const gsr_adam_moments *m, const gsr_adam_moments *v,
+                                    const gsr_adam_config *cfg, int32_t *step_dev, const gsr_grads *grads_out,
+                                    void *stream) {
+  gsr_status st = backward_common(c, g, cams, n_views, ws_base, ws_bytes, fwd, dL_dimage);
+  if (st != GSR_OK) return st;
+  AdamArgs a{};
+  if ((st = adam_args(c, params, m, v, cfg, step_dev, a)) != GSR_OK) return st;
+  MutPtrs gr{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (grads_out) {
+    gr = mut_ptrs(grads_out);
+    if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient output pointer is NULL");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Ws ws = make_ws(c, ws_base);
+  launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
+  launch_step_inc(step_dev, s);
+  launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a, s);
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_binning(gsr_ctx *c, void *ws_base, uint64_t *keys, uint32_t *vals, uint32_t *tile_csr,
+                             void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (!ws_base || !keys || !vals || !tile_csr) return fail(c, GSR_ERR_INVALID_ARG, "NULL argument to gsr_debug_binning");
+  launch_debug_binning(c->views_d, make_ws(c, ws_base), c->sz, keys, vals, tile_csr, static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+static gsr_status read_scalars(gsr_ctx *c, void *ws_base, void *stream, uint32_t out[kNumScalars]) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (!ws_base) return fail(c, GSR_ERR_INVALID_ARG, "workspace is NULL");
+  GSR_HIP(c, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  GSR_HIP(c, hipMemcpy(out, static_cast<char *>(ws_base) + c->lay.scalars, kNumScalars * 4, hipMemcpyDeviceToHost));
+  return GSR_OK;
+}
+
+gsr_status gsr_check(gsr_ctx *c, void *ws_base, void *stream) {
+  uint32_t sc[kNumScalars];
+  gsr_status st = read_scalars(c, ws_base, stream, sc);
+  if (st != GSR_OK) return st;
+  if (sc[kOverflow] == 1u)
+    return fail(c, GSR_ERR_CAPACITY, "capacity exceeded: %u records (capacity %u), %u pairs (capacity %u)",
+                sc[kNumRecords], c->sz.cap_rec, sc[kNumPairs], c->sz.cap_pairs);
+  if (sc[kOverflow] != 0u) return fail(c, GSR_ERR_HIP, "internal binning inconsistency (code %u)", sc[kOverflow]);
+  return GSR_OK;
+}
+
+gsr_status gsr_required_capacity(gsr_ctx *c, void *ws_base, int64_t *records, int64_t *pairs, int64_t *tiles,
+                                 void *stream) {
+  uint32_t sc[kNumScalars];
+  gsr_status st = read_scalars(c, ws_base, stream, sc);
+  if (st != GSR_OK) return st;
+  if (records) *records = sc[kNumRecords];
+  if (pairs) *pairs = sc[kNumPairs];
+  if (tiles) *tiles = c->sz.t_tot;
+  return GSR_OK;
+}
+
+gsr_status gsr_set_sort_routing(gsr_ctx *c, uint32_t small_max, int32_t force_class) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (small_max < 1 || small_max > 256 || force_class < -1 || force_class > 2)
+    return fail(c, GSR_ERR_INVALID_ARG, "small_max must be in 1..256 and force_class in -1..2");
+  c->sort_small_max = small_max;
+  c->sort_force_class = force_class;
+  return GSR_OK;
+}
+
+const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Wavefront (64 lanes) and workgroup scan / reduction helpers.
+#pragma once
+
+#include "common.hpp"
+
+namespace gsr {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+// Inclusive prefix sum over the wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads; `total` gets the sum.
+// `lds` must hold NT / 64 elements.  Contains two barriers.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *lds, T &total) {
+  constexpr int NW = NT / kWave;
+  const T incl = wave_incl_scan(x);
+  if (lane_id() == kWave - 1) lds[wave_id()] = incl;
+  __syncthreads();
+  T before = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const T s = lds[w];
+    if (w < wave_id()) before += s;
+    sum += s;
+  }
+  __syncthreads();
+  total = sum;
+  return before + incl - x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_or(T x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_and(T x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) x &= __shfl_xor(x, d, kWave);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_max(T x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_xor(x, d, kWave);
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Sum over the wave with DPP row operations; the total is valid in lane 63.
+// Must be called with all 64 lanes active.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  int x = __float_as_int(v);
+  // quad butterflies: lanes (0,1,2,3) -> (1,0,3,2) then (2,3,0,1)
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
+  // rotate within each row of 16 by 4, then by 8: every lane holds its row sum
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
+  // row broadcasts: lane 15 of rows 0/2 into rows 1/3, then lane 31 into rows 2/3
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false)));
+  return __int_as_float(x);
+}
+
+// Tile visited by workgroup `bid` of a grid of `grid` workgroups over `total`
+// tiles.  Consecutive workgroups are dispatched round-robin over the 8 XCDs;
+// this mapping gives each XCD one contiguous run of tiles so neighbouring
+// tiles, which share most of their Gaussians, hit the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t grid) {
+  const uint32_t per_xcd = grid / 8u;  // grid is a multiple of 8
+  return (bid % 8u) * per_xcd + bid / 8u;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewInfo *__restrict__ views, int n_views, uint32_t tile) {
+  int v = 0;
+  while (v + 1 < n_views && views[v + 1].tile_base <= tile) ++v;
+  return v;
+}
+
+}  // namespace gsr

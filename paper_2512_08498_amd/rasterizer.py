@@ -1,0 +1,258 @@
+"""Python binding over the C ABI: device memory and streams come from torch,
+every step of the rasterizer runs in the HIP library.
+
+``Rasterizer`` owns a context, a plan for one batch of views and the device
+workspace; ``RasterizeFn`` is the torch.autograd.Function around
+render_forward / render_backward; ``FusedAdam`` is the optimiser step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAM_NAMES = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 2.5e-3 / 20.0)
+
+
+def _vp(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def camera_rows(cams) -> np.ndarray:
+    """[V, 18] float32 rows in the gsr_camera layout (width/height as int32 bits)."""
+    rows = np.zeros((len(cams), 18), dtype=np.float32)
+    for i, c in enumerate(cams):
+        rows[i, 0:9] = np.asarray(c.R, np.float32).reshape(-1)
+        rows[i, 9:12] = np.asarray(c.t, np.float32).reshape(-1)
+        rows[i, 12:16] = (c.fx, c.fy, c.cx, c.cy)
+        rows[i, 16:18] = np.array([c.width, c.height], np.int32).view(np.float32)
+    return rows
+
+
+def _check_param(name, t: torch.Tensor, shape, device):
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected contiguous float32 {tuple(shape)} on {device}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device} (contiguous={t.is_contiguous()})")
+
+
+class Rasterizer:
+    """One planned batch of views over n Gaussians of a fixed SH degree."""
+
+    def __init__(self, cams: Sequence, n: int, sh_degree: int, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
+                 capacity_records: int = 0, capacity_pairs: int = 0, device="cuda", cams_device=None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n = int(n)
+        self.sh_degree = int(sh_degree)
+        self.tile_size = int(tile_size)
+        self.bg = tuple(float(b) for b in bg)
+        self.views = len(cams)
+        self.sizes = [(int(c.width), int(c.height)) for c in cams]
+        rows = camera_rows(cams)
+        self._cams_host = (L.Camera * self.views)()
+        C.memmove(self._cams_host, rows.ctypes.data, rows.nbytes)
+        self.cams_dev = cams_device if cams_device is not None else torch.from_numpy(rows).to(self.device)
+        self.ctx = C.c_void_p()
+        L.check(None, self.lib.gsr_create(C.byref(self.ctx)))
+        self.workspace = None
+        self._plan(capacity_records, capacity_pairs)
+
+    # -- plan / workspace ------------------------------------------------------------------
+    def _plan(self, cap_rec, cap_pairs):
+        opts = L.PlanOptions(self.tile_size, int(cap_rec), int(cap_pairs), (C.c_float * 3)(*self.bg))
+        ws = C.c_size_t()
+        pix = (C.c_int64 * (self.views + 1))()
+        self._check(self.lib.gsr_plan(self.ctx, self._cams_host, self.views, self.n, self.sh_degree,
+                                      C.byref(opts), C.byref(ws), pix))
+        self.capacity = (int(cap_rec), int(cap_pairs))
+        self.ws_bytes = int(ws.value)
+        self.pix_off = [int(p) for p in pix]
+        self.total_px = self.pix_off[-1]
+        self.workspace = None
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def _check(self, status):
+        L.check(self.ctx, status)
+
+    def stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.gsr_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _gaussians(self, p: Dict[str, torch.Tensor]) -> L.Gaussians:
+        n, k = self.n, (self.sh_degree + 1) ** 2
+        shapes = dict(mean=(3, n), log_scale=(3, n), quat=(4, n), opacity_logit=(n,), sh=(k, 3, n))
+        for name in PARAM_NAMES:
+            _check_param(name, p[name], shapes[name], self.device)
+        return L.Gaussians(n, self.sh_degree, *(p[name].data_ptr() for name in PARAM_NAMES))
+
+    def new_fwd_out(self):
+        px = self.total_px
+        return dict(image=torch.empty(3 * px, dtype=torch.float32, device=self.device),
+                    t_final=torch.empty(px, dtype=torch.float32, device=self.device),
+                    last_pos=torch.empty(px, dtype=torch.int32, device=self.device),
+                    n_contrib=torch.empty(px, dtype=torch.int32, device=self.device))
+
+    @staticmethod
+    def _fwd_struct(out) -> L.FwdOut:
+        return L.FwdOut(out["image"].data_ptr(), out["t_final"].data_ptr(), out["last_pos"].data_ptr(),
+                        out["n_contrib"].data_ptr())
+
+    def view_images(self, flat: torch.Tensor):
+        """Per-view [3, H, W] views of a flat image buffer."""
+        return [flat[3 * self.pix_off[v]:3 * self.pix_off[v + 1]].view(3, h, w)
+                for v, (w, h) in enumerate(self.sizes)]
+
+    def view_maps(self, flat: torch.Tensor):
+        """Per-view [H, W] views of a flat per-pixel buffer."""
+        return [flat[self.pix_off[v]:self.pix_off[v + 1]].view(h, w) for v, (w, h) in enumerate(self.sizes)]
+
+    # -- calls -----------------------------------------------------------------------------
+    def forward(self, params, out=None, check=True, cams_dev=None):
+        """Render all views.  With ``check`` the call synchronises, and on a
+        capacity overflow re-plans with the sizes the forward reported and
+        renders again."""
+        out = out if out is not None else self.new_fwd_out()
+        g = self._gaussians(params)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self._check(self.lib.gsr_render_forward(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
+                                                self.ws_bytes, C.byref(self._fwd_struct(out)), self.stream()))
+        if check:
+            st = self.lib.gsr_check(self.ctx, _vp(self.workspace), self.stream())
+            if st == L.GSR_ERR_CAPACITY:
+                rec, pairs, _ = self.required_capacity()
+                self._plan(max(int(rec * 1.25) + 1024, self.capacity[0]), max(int(pairs * 1.25) + 4096,
+                                                                                self.capacity[1]))
+                return self.forward(params, out=out, check=True, cams_dev=cams_dev)
+            self._check(st)
+        return out
+
+    def required_capacity(self):
+        r, p, t = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.lib.gsr_required_capacity(self.ctx, _vp(self.workspace), C.byref(r), C.byref(p),
+                                                   C.byref(t), self.stream()))
+        return r.value, p.value, t.value
+
+    def check(self):
+        self._check(self.lib.gsr_check(self.ctx, _vp(self.workspace), self.stream()))
+
+    def backward(self, params, fwd, dL_dimage, grads=None, accumulate=False, cams_dev=None):
+        g = self._gaussians(params)
+        if grads is None:
+            grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+        gr = L.Grads(*(grads[k].data_ptr() for k in PARAM_NAMES))
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        dl = dL_dimage.contiguous()
+        self._check(self.lib.gsr_render_backward(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
+                                                 self.ws_bytes, C.byref(self._fwd_struct(fwd)), _vp(dl),
+                                                 C.byref(gr), 1 if accumulate else 0, self.stream()))
+        return grads
+
+    def backward_adam(self, params, fwd, dL_dimage, opt: "FusedAdam", grads_out=None, cams_dev=None):
+        g = self._gaussians(params)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        go = C.byref(L.Grads(*(grads_out[k].data_ptr() for k in PARAM_NAMES))) if grads_out is not None else None
+        self._check(self.lib.gsr_render_backward_adam(
+            self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace), self.ws_bytes,
+            C.byref(self._fwd_struct(fwd)), _vp(dL_dimage), C.byref(opt.param_struct(params)),
+            C.byref(opt.m_struct()), C.byref(opt.v_struct()), C.byref(opt.config), _vp(opt.step), go,
+            self.stream()))
+
+    def l1_loss(self, image, target, loss_out=None, dl_out=None):
+        loss_out = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=self.device)
+        dl_out = dl_out if dl_out is not None else torch.empty_like(image)
+        self._check(self.lib.gsr_l1_loss(self.ctx, _vp(image), _vp(target), image.numel(), _vp(loss_out),
+                                         _vp(dl_out), self.stream()))
+        return loss_out, dl_out
+
+    def set_sort_routing(self, small_max=256, force_class=-1):
+        self._check(self.lib.gsr_set_sort_routing(self.ctx, int(small_max), int(force_class)))
+
+    def debug_binning(self):
+        """(keys uint64, values uint32, tile CSR) of the last forward, as numpy."""
+        _, pairs, tiles = self.required_capacity()
+        keys = torch.empty(max(pairs, 1), dtype=torch.int64, device=self.device)
+        vals = torch.empty(max(pairs, 1), dtype=torch.int32, device=self.device)
+        csr = torch.empty(tiles + 1, dtype=torch.int32, device=self.device)
+        self._check(self.lib.gsr_debug_binning(self.ctx, _vp(self.workspace), _vp(keys), _vp(vals), _vp(csr),
+                                               self.stream()))
+        torch.cuda.synchronize(self.device)
+        return (keys.cpu().numpy().view(np.uint64)[:pairs], vals.cpu().numpy().view(np.uint32)[:pairs],
+                csr.cpu().numpy().view(np.uint32).astype(np.int64))
+
+
+class FusedAdam:
+    """Dense Adam over the five parameter tensors (six learning-rate groups:
+    mean, log_scale, quat, opacity_logit, SH degree 0, higher SH)."""
+
+    def __init__(self, rast: Rasterizer, params, lr=DEFAULT_LR, betas=(0.9, 0.999), eps=1e-15):
+        self.rast = rast
+        self.params = params
+        self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.step = torch.zeros(1, dtype=torch.int32, device=rast.device)
+        self.config = L.AdamConfig((C.c_float * 6)(*lr), betas[0], betas[1], eps)
+
+    def param_struct(self, params=None):
+        p = params if params is not None else self.params
+        return L.Grads(*(p[k].data_ptr() for k in PARAM_NAMES))
+
+    def m_struct(self):
+        return L.Grads(*(self.m[k].data_ptr() for k in PARAM_NAMES))
+
+    def v_struct(self):
+        return L.Grads(*(self.v[k].data_ptr() for k in PARAM_NAMES))
+
+    def apply(self, grads):
+        r = self.rast
+        r._check(r.lib.gsr_adam_step(r.ctx, C.byref(self.param_struct()),
+                                     C.byref(L.Grads(*(grads[k].data_ptr() for k in PARAM_NAMES))),
+                                     C.byref(self.m_struct()), C.byref(self.v_struct()), C.byref(self.config),
+                                     _vp(self.step), r.n, r.sh_degree, r.stream()))
+
+
+class RasterizeFn(torch.autograd.Function):
+    """image = render(Gaussians) with the hand-written adjoint as backward.
+
+    The workspace of ``rast`` carries the binning state from forward to
+    backward, so no other forward of the same rasterizer may run in between.
+    """
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, mean, log_scale, quat, opacity_logit, sh):
+        params = dict(mean=mean.contiguous(), log_scale=log_scale.contiguous(), quat=quat.contiguous(),
+                      opacity_logit=opacity_logit.contiguous(), sh=sh.contiguous())
+        out = rast.forward(params)
+        ctx.rast = rast
+        ctx.fwd = out
+        ctx.save_for_backward(*(params[k] for k in PARAM_NAMES))
+        ctx.mark_non_differentiable(out["t_final"])
+        return out["image"]
+
+    @staticmethod
+    def backward(ctx, d_image):
+        params = dict(zip(PARAM_NAMES, ctx.saved_tensors))
+        grads = ctx.rast.backward(params, ctx.fwd, d_image.contiguous())
+        return (None,) + tuple(grads[k] for k in PARAM_NAMES)
+
+
+def rasterize(rast: Rasterizer, params):
+    """Differentiable flat image of all views (see Rasterizer.view_images)."""
+    return RasterizeFn.apply(rast, *(params[k] for k in PARAM_NAMES))
