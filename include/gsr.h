@@ -199,6 +199,27 @@ gsr_status gsr_check(gsr_ctx *ctx, void *workspace, void *stream);
 gsr_status gsr_required_capacity(gsr_ctx *ctx, void *workspace, int64_t *records, int64_t *pairs,
                                  int64_t *tiles, void *stream);
 
+/* Stage timing.  While enabled, every render / loss / Adam call records HIP
+ * events around each of its stages on its own stream, waits for them, and
+ * accumulates the elapsed milliseconds per stage (so it synchronises: not
+ * for use under graph capture).  gsr_profile_read copies the per-stage
+ * totals and call counts into HOST arrays of GSR_N_STAGES entries, indexed
+ * by gsr_stage, and optionally resets them.                               */
+#define GSR_N_STAGES 9
+typedef enum {
+  GSR_STAGE_PREPROCESS = 0, /* projection, record compaction, tile counting  */
+  GSR_STAGE_BINNING = 1,    /* list offsets and key emission                 */
+  GSR_STAGE_SORT = 2,       /* per-tile radix sort                           */
+  GSR_STAGE_RASTER_FWD = 3, /* forward compositing                           */
+  GSR_STAGE_LOSS = 4,       /* L1 loss and its gradient                      */
+  GSR_STAGE_RASTER_BWD = 5, /* backward compositing                          */
+  GSR_STAGE_REDUCE = 6,     /* per-record sum of the per-tile partials       */
+  GSR_STAGE_PRE_BWD = 7,    /* per-Gaussian chain rule (with Adam if fused)  */
+  GSR_STAGE_ADAM = 8        /* standalone Adam step                          */
+} gsr_stage;
+gsr_status gsr_profile(gsr_ctx *ctx, int32_t enable);
+gsr_status gsr_profile_read(gsr_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
+
 /* Test hook for the per-tile sort: tile lists longer than small_max
  * (1..256, default 256) leave the 256-entry LDS sort; force_class >= 0 sends
  * every such list to at least size class force_class (0: 2048-entry LDS sort,

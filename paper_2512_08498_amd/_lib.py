@@ -17,6 +17,9 @@ GSR_ERR_HIP = -3
 GSR_ERR_UNSUPPORTED = -4
 GSR_ERR_NOT_PLANNED = -5
 
+N_STAGES = 9
+STAGE_NAMES = ("preprocess", "binning", "sort", "raster_fwd", "loss", "raster_bwd", "reduce", "pre_bwd", "adam")
+
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "CAPACITY", -3: "HIP", -4: "UNSUPPORTED", -5: "NOT_PLANNED"}
 
 P = C.c_void_p
@@ -69,6 +72,8 @@ _SIGS = {
     "gsr_check": [P, P, P],
     "gsr_required_capacity": [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P],
     "gsr_set_sort_routing": [P, C.c_uint32, C.c_int32],
+    "gsr_profile": [P, C.c_int32],
+    "gsr_profile_read": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "gsr_last_error": [P],
 }
 

@@ -31,6 +31,7 @@ void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, flo
                        uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st);
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);
+void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
                     const MutPtrs *grads, int accumulate, const AdamArgs *adam, hipStream_t st);
 void launch_adam(const MutPtrs &grads, const AdamArgs &a, int64_t n, int sh_degree, hipStream_t st);

@@ -232,6 +232,9 @@ void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, con
         break;
     }
   }
+}
+
+void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st) {
   const uint32_t blocks = std::min<uint32_t>((sz.cap_rec + 255) / 256, 8192u);
   k_reduce_pairs<<<std::max(blocks, 1u), 256, 0, st>>>(ws);
 }

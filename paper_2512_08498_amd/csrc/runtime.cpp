@@ -42,6 +42,11 @@ struct gsr_ctx {
   uint32_t *loss_ticket = nullptr;
   uint32_t sort_small_max = 256;
   int32_t sort_force_class = -1;
+  // stage timing
+  bool prof = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double prof_ms[GSR_N_STAGES] = {};
+  int64_t prof_calls[GSR_N_STAGES] = {};
 };
 
 namespace {
@@ -63,6 +68,25 @@ gsr_status fail(gsr_ctx *c, gsr_status s, const char *fmt, ...) {
     hipError_t e_ = (call);                                                                 \
     if (e_ != hipSuccess) return fail(ctx, GSR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
+
+// Brackets one stage with HIP events when stage timing is on.
+struct StageTimer {
+  gsr_ctx *c;
+  int stage;
+  hipStream_t s;
+  StageTimer(gsr_ctx *c_, int stage_, hipStream_t s_) : c(c_), stage(stage_), s(s_) {
+    if (c->prof) (void)hipEventRecord(c->ev0, s);
+  }
+  ~StageTimer() {
+    if (!c->prof) return;
+    float ms = 0.0f;
+    if (hipEventRecord(c->ev1, s) == hipSuccess && hipEventSynchronize(c->ev1) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+      c->prof_ms[stage] += ms;
+      c->prof_calls[stage] += 1;
+    }
+  }
+};
 
 Ws make_ws(const gsr_ctx *c, void *base) {
   char *b = static_cast<char *>(base);
@@ -181,6 +205,8 @@ gsr_status gsr_create(gsr_ctx **out) {
 void gsr_destroy(gsr_ctx *c) {
   if (!c) return;
   if (c->views_d) (void)hipFree(c->views_d);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->loss_partials) (void)hipFree(c->loss_partials);
   if (c->loss_ticket) (void)hipFree(c->loss_ticket);
   delete c;
@@ -265,11 +291,23 @@ gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_came
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
   const Cam *cm = reinterpret_cast<const Cam *>(cams);
-  launch_zero(ws.scalars, (c->lay.zero_end - c->lay.scalars) / 4, s);
-  launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, s);
-  launch_binning(c->views_d, ws, c->sz, s);
-  launch_sort(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
-  launch_raster_fwd(c->views_d, ws, c->sz, out->image, out->t_final, out->last_pos, out->n_contrib, s);
+  {
+    StageTimer tm(c, GSR_STAGE_PREPROCESS, s);
+    launch_zero(ws.scalars, (c->lay.zero_end - c->lay.scalars) / 4, s);
+    launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_BINNING, s);
+    launch_binning(c->views_d, ws, c->sz, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_SORT, s);
+    launch_sort(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_RASTER_FWD, s);
+    launch_raster_fwd(c->views_d, ws, c->sz, out->image, out->t_final, out->last_pos, out->n_contrib, s);
+  }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
 }
@@ -279,8 +317,11 @@ gsr_status gsr_l1_loss(gsr_ctx *c, const float *image, const float *target, int6
   if (!c) return GSR_ERR_INVALID_ARG;
   if (!image || !target || !loss_out || !dL_dimage) return fail(c, GSR_ERR_INVALID_ARG, "NULL argument to gsr_l1_loss");
   if (n_elems <= 0) return fail(c, GSR_ERR_INVALID_ARG, "n_elems must be positive");
-  launch_l1(image, target, n_elems, loss_out, dL_dimage, c->loss_partials, c->loss_ticket,
-            static_cast<hipStream_t>(stream));
+  {
+    StageTimer tm(c, GSR_STAGE_LOSS, static_cast<hipStream_t>(stream));
+    launch_l1(image, target, n_elems, loss_out, dL_dimage, c->loss_partials, c->loss_ticket,
+              static_cast<hipStream_t>(stream));
+  }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
 }
@@ -305,9 +346,19 @@ gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_cam
   if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient pointer is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
-  launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
-  launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr,
-                 accumulate ? 1 : 0, nullptr, s);
+  {
+    StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
+    launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_REDUCE, s);
+    launch_reduce_pairs(ws, c->sz, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
+    launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr,
+                   accumulate ? 1 : 0, nullptr, s);
+  }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
 }
@@ -346,8 +397,11 @@ gsr_status gsr_adam_step(gsr_ctx *c, const gsr_grads *params, const gsr_grads *g
   c->n = keep_n;
   if (st != GSR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  launch_step_inc(step_dev, s);
-  launch_adam(gr, a, n, sh_degree, s);
+  {
+    StageTimer tm(c, GSR_STAGE_ADAM, s);
+    launch_step_inc(step_dev, s);
+    launch_adam(gr, a, n, sh_degree, s);
+  }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
 }
@@ -368,9 +422,19 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
-  launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
-  launch_step_inc(step_dev, s);
-  launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a, s);
+  {
+    StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
+    launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_REDUCE, s);
+    launch_reduce_pairs(ws, c->sz, s);
+  }
+  {
+    StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
+    launch_step_inc(step_dev, s);
+    launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a, s);
+  }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
 }
@@ -422,6 +486,29 @@ gsr_status gsr_set_sort_routing(gsr_ctx *c, uint32_t small_max, int32_t force_cl
     return fail(c, GSR_ERR_INVALID_ARG, "small_max must be in 1..256 and force_class in -1..2");
   c->sort_small_max = small_max;
   c->sort_force_class = force_class;
+  return GSR_OK;
+}
+
+gsr_status gsr_profile(gsr_ctx *c, int32_t enable) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (enable && !c->ev0) {
+    GSR_HIP(c, hipEventCreate(&c->ev0));
+    GSR_HIP(c, hipEventCreate(&c->ev1));
+  }
+  c->prof = enable != 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_profile_read(gsr_ctx *c, double *ms, int64_t *calls, int32_t reset) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  for (int k = 0; k < GSR_N_STAGES; ++k) {
+    if (ms) ms[k] = c->prof_ms[k];
+    if (calls) calls[k] = c->prof_calls[k];
+    if (reset) {
+      c->prof_ms[k] = 0.0;
+      c->prof_calls[k] = 0;
+    }
+  }
   return GSR_OK;
 }
 

@@ -182,6 +182,17 @@ class Rasterizer:
                                          _vp(dl_out), self.stream()))
         return loss_out, dl_out
 
+    def profile(self, enable=True):
+        """Per-stage HIP-event timing of subsequent calls (synchronising)."""
+        self._check(self.lib.gsr_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self, reset=True):
+        """{stage: (total ms, calls)} accumulated since the last reset."""
+        ms = (C.c_double * L.N_STAGES)()
+        calls = (C.c_int64 * L.N_STAGES)()
+        self._check(self.lib.gsr_profile_read(self.ctx, ms, calls, 1 if reset else 0))
+        return {name: (ms[i], calls[i]) for i, name in enumerate(L.STAGE_NAMES)}
+
     def set_sort_routing(self, small_max=256, force_class=-1):
         self._check(self.lib.gsr_set_sort_routing(self.ctx, int(small_max), int(force_class)))
 

@@ -1,0 +1,295 @@
+"""GPU tests of the loss, the optimiser, invariances, the sort size classes,
+capacity handling and edge cases (all through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import device_params, grads_to_host, host_outputs, log, render_gpu
+from oracle.adam64 import adam_step
+from oracle.binning import tile_lists
+from oracle.render64 import render
+from paper_2512_08498_amd import PARAM_NAMES, FusedAdam, Rasterizer
+from paper_2512_08498_amd import _lib as L
+from tiny_scenes import camera, logit, mini_rig, scene
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def test_l1_loss_and_gradient(cfg1):
+    scene_, cams, targets = cfg1
+    rast, params, out = render_gpu(scene_, cams)
+    tgt = torch.from_numpy(targets[0].reshape(-1)).cuda()
+    loss, dl = rast.l1_loss(out["image"], tgt)
+    img = out["image"].cpu().numpy().astype(np.float64)
+    d = img - targets[0].reshape(-1)
+    assert abs(loss.item() - np.abs(d).mean()) <= 1e-6 * np.abs(d).mean()
+    assert np.array_equal(dl.cpu().numpy(), (np.sign(d) / d.size).astype(np.float32))
+    loss2, _ = rast.l1_loss(out["image"], tgt)
+    assert loss2.item() == loss.item()  # fixed-order reduction
+
+
+def _rand_state(scene_, seed):
+    rng = np.random.default_rng(seed)
+    return {k: rng.standard_normal(v.shape).astype(np.float32) for k, v in scene_.arrays().items()}
+
+
+def test_adam_matches_oracle_over_steps(cfg1):
+    scene_, cams, _ = cfg1
+    rast = Rasterizer(cams, scene_.n, scene_.sh_degree)
+    params = device_params(scene_)
+    lr = (1e-3, 2e-3, 3e-3, 4e-3, 5e-3, 6e-3)
+    opt = FusedAdam(rast, params, lr=lr)
+    p = {k: v.astype(np.float64) for k, v in scene_.arrays().items()}
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v_ = {k: np.zeros_like(v) for k, v in p.items()}
+    groups = dict(mean=0, log_scale=1, quat=2, opacity_logit=3)
+    for it in range(4):
+        g = _rand_state(scene_, 100 + it)
+        opt.apply({k: torch.from_numpy(x).cuda() for k, x in g.items()})
+        for k in PARAM_NAMES:
+            if k == "sh":
+                n = scene_.n
+                flat_p, flat_g = p[k].reshape(-1), g[k].astype(np.float64).reshape(-1)
+                fm, fv = m[k].reshape(-1), v_[k].reshape(-1)
+                a = adam_step(flat_p[:3 * n], flat_g[:3 * n], fm[:3 * n], fv[:3 * n], it, lr[4])
+                b = adam_step(flat_p[3 * n:], flat_g[3 * n:], fm[3 * n:], fv[3 * n:], it, lr[5])
+                p[k] = np.concatenate([a[0], b[0]]).reshape(p[k].shape)
+                m[k] = np.concatenate([a[1], b[1]]).reshape(p[k].shape)
+                v_[k] = np.concatenate([a[2], b[2]]).reshape(p[k].shape)
+            else:
+                p[k], m[k], v_[k] = adam_step(p[k], g[k].astype(np.float64), m[k], v_[k], it, lr[groups[k]])
+    torch.cuda.synchronize()
+    assert int(opt.step.item()) == 4
+    for k in PARAM_NAMES:
+        got = params[k].cpu().numpy().astype(np.float64)
+        step_scale = max(lr)
+        assert np.abs(got - p[k]).max() <= 1e-5 * step_scale + 1e-6 * np.abs(p[k]).max(), k
+
+
+def test_fused_backward_adam_equals_backward_then_adam():
+    scene_, cams = mini_rig()
+    rng = np.random.default_rng(5)
+    rast, params, out = render_gpu(scene_, cams)
+    dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-4).cuda()
+    grads = rast.backward(params, out, dl)
+    p1 = {k: v.clone() for k, v in params.items()}
+    opt1 = FusedAdam(rast, p1)
+    opt1.apply(grads)
+    p2 = {k: v.clone() for k, v in params.items()}
+    opt2 = FusedAdam(rast, p2)
+    g_out = {k: torch.empty_like(v) for k, v in params.items()}
+    rast.backward_adam(p2, out, dl, opt2, grads_out=g_out)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        assert torch.equal(g_out[k], grads[k]), k
+        assert torch.allclose(p1[k], p2[k], rtol=0, atol=1e-7), k
+        assert torch.equal(opt1.m[k], opt2.m[k]), k
+
+
+def test_forward_bitwise_invariant_to_tile_size_and_repeatable(cfg1):
+    scene_, cams, _ = cfg1
+    ref = None
+    for ts in (16, 8, 32, 16):
+        rast, params, out = render_gpu(scene_, cams, ts=ts)
+        cur = (out["image"].cpu().numpy(), out["t_final"].cpu().numpy(), out["n_contrib"].cpu().numpy())
+        if ref is None:
+            ref = cur
+        for a, b in zip(ref, cur):
+            assert np.array_equal(a, b), ts
+
+
+def test_batched_equals_per_view_bitwise():
+    scene_, cams = make_config(3, scale=0.01)
+    rast, params, out = render_gpu(scene_, cams)
+    imgs = [x.cpu().numpy() for x in rast.view_images(out["image"])]
+    rng = np.random.default_rng(9)
+    dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-5).cuda()
+    g_b = grads_to_host(rast.backward(params, out, dl))
+    g_sum = {k: np.zeros_like(v) for k, v in g_b.items()}
+    for v, c in enumerate(cams):
+        r1, p1, o1 = render_gpu(scene_, [c])
+        assert np.array_equal(r1.view_images(o1["image"])[0].cpu().numpy(), imgs[v]), v
+        g1 = grads_to_host(r1.backward(p1, o1, dl[3 * rast.pix_off[v]:3 * rast.pix_off[v + 1]].contiguous()))
+        for k in g_sum:
+            g_sum[k] += g1[k]
+    for k in g_b:
+        scale = np.abs(g_b[k]).max()
+        assert np.abs(g_b[k] - g_sum[k]).max() <= 1e-5 * scale, k
+
+
+def test_backward_is_deterministic():
+    scene_, cams = mini_rig()
+    rast, params, out = render_gpu(scene_, cams)
+    dl = torch.from_numpy(np.random.default_rng(1).standard_normal(3 * rast.total_px).astype(np.float32)).cuda()
+    a = rast.backward(params, out, dl)
+    b = rast.backward(params, out, dl)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_graph_replays_match_eager():
+    scene_, cams = make_config(3, scale=0.005)
+    rast, params, _ = render_gpu(scene_, cams)
+    out = rast.new_fwd_out()
+    dl = torch.from_numpy(np.random.default_rng(2).standard_normal(3 * rast.total_px).astype(np.float32)).cuda()
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+
+    def step():
+        rast.forward(params, out=out, check=False)
+        rast.backward(params, out, dl, grads=grads)
+
+    step()
+    torch.cuda.synchronize()
+    ref_img = out["image"].clone()
+    ref_g = {k: v.clone() for k, v in grads.items()}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(4):
+        out["image"].zero_()
+        for v in grads.values():
+            v.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["image"], ref_img), rep
+        for k in PARAM_NAMES:
+            assert torch.equal(grads[k], ref_g[k]), (rep, k)
+        step()  # eager work between replays
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("routing", [(1, 0), (1, 1), (1, 2), (64, 2)])
+def test_every_sort_path_is_bit_exact(routing):
+    scene_, cams = make_config(3, scale=0.01)
+    log(f"sort routing {routing}")
+    rast, params, out = render_gpu(scene_, cams, routing=routing)
+    keys, vals, csr = rast.debug_binning()
+    okeys, ovals, ocsr = tile_lists(scene_, cams, 16)
+    assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals) and np.array_equal(csr, ocsr)
+    ref, _, ref_out = render_gpu(scene_, cams)
+    assert torch.equal(out["image"], ref_out["image"])
+
+
+def test_sort_orders_equal_depths_by_gaussian_index():
+    # 40 Gaussians at identical depth: every list is one long tie
+    n = 40
+    rng = np.random.default_rng(4)
+    means = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n), np.full(n, 3.0)], 1)
+    sc = scene(means, np.full((n, 3), -2.0), [[1, 0, 0, 0]] * n, rng.normal(0, 1, n),
+               colours=rng.uniform(0, 1, (n, 3)))
+    cams = [camera(60.0)]
+    for routing in (None, (1, 0), (1, 2)):
+        rast, params, out = render_gpu(sc, cams, routing=routing)
+        keys, vals, csr = rast.debug_binning()
+        okeys, ovals, ocsr = tile_lists(sc, cams, 16)
+        assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals)
+
+
+def test_capacity_overflow_reports_and_retries(cfg1):
+    scene_, cams, _ = cfg1
+    rast = Rasterizer(cams, scene_.n, scene_.sh_degree, capacity_records=10, capacity_pairs=10)
+    params = device_params(scene_)
+    out = rast.new_fwd_out()
+    rast.forward(params, out=out, check=False)
+    with pytest.raises(L.GsrError) as e:
+        rast.check()
+    assert e.value.status == L.GSR_ERR_CAPACITY
+    rec, pairs, _ = rast.required_capacity()
+    assert rec > 10 and pairs > 10
+    out2 = rast.forward(params)  # re-plans and renders again
+    ref = render(scene_, cams)[0]
+    img = rast.view_images(out2["image"])[0].cpu().numpy()
+    ok = ~ref["ambiguous"]
+    assert np.abs(img - ref["image"])[:, ok].max() <= 1e-5
+
+
+def test_abi_rejects_invalid_arguments(cfg1):
+    scene_, cams, _ = cfg1
+    rast = Rasterizer(cams, scene_.n, scene_.sh_degree)
+    lib = rast.lib
+    import ctypes as C
+    bad = (L.Camera * 1)()
+    C.memmove(bad, np.zeros(18, np.float32).ctypes.data, 72)
+    ws, pix = C.c_size_t(), (C.c_int64 * 2)()
+    opts = L.PlanOptions(16, 0, 0, (C.c_float * 3)(0, 0, 0))
+    assert lib.gsr_plan(rast.ctx, bad, 1, 10, 0, C.byref(opts), C.byref(ws), pix) == L.GSR_ERR_INVALID_ARG
+    good = rast._cams_host
+    assert lib.gsr_plan(rast.ctx, good, 0, 10, 0, C.byref(opts), C.byref(ws), pix) == L.GSR_ERR_INVALID_ARG
+    assert lib.gsr_plan(rast.ctx, good, 1, 10, 4, C.byref(opts), C.byref(ws), pix) == L.GSR_ERR_UNSUPPORTED
+    opts.tile_size = 12
+    assert lib.gsr_plan(rast.ctx, good, 1, 10, 0, C.byref(opts), C.byref(ws), pix) == L.GSR_ERR_INVALID_ARG
+    # a render against a stale plan and a short workspace
+    rast2 = Rasterizer(cams, scene_.n, scene_.sh_degree)
+    params = device_params(scene_)
+    g = rast2._gaussians(params)
+    out = rast2.new_fwd_out()
+    fo = rast2._fwd_struct(out)
+    st = lib.gsr_render_forward(rast2.ctx, C.byref(g), C.c_void_p(rast2.cams_dev.data_ptr()), 1,
+                                C.c_void_p(rast2.workspace.data_ptr()), 16, C.byref(fo), rast2.stream())
+    assert st == L.GSR_ERR_INVALID_ARG and b"workspace" in lib.gsr_last_error(rast2.ctx)
+    g.n = scene_.n + 1
+    st = lib.gsr_render_forward(rast2.ctx, C.byref(g), C.c_void_p(rast2.cams_dev.data_ptr()), 1,
+                                C.c_void_p(rast2.workspace.data_ptr()), rast2.ws_bytes, C.byref(fo), rast2.stream())
+    assert st == L.GSR_ERR_NOT_PLANNED
+    assert lib.gsr_set_sort_routing(rast2.ctx, 0, -1) == L.GSR_ERR_INVALID_ARG
+
+
+def _edge_check(sc, cams, ts=16):
+    rast, params, out = render_gpu(sc, cams, ts=ts)
+    ora = render(sc, cams)
+    imgs, T, cnt, _ = host_outputs(rast, out)
+    for v in range(len(cams)):
+        ok = ~ora[v]["ambiguous"]
+        assert np.abs(imgs[v] - ora[v]["image"])[:, ok].max(initial=0.0) <= 1e-5
+        assert np.array_equal(cnt[v][ok], ora[v]["count"][ok])
+    if sc.n:
+        keys, vals, csr = rast.debug_binning()
+        okeys, ovals, ocsr = tile_lists(sc, cams, ts)
+        assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals) and np.array_equal(csr, ocsr)
+        dl = torch.ones(3 * rast.total_px, device="cuda") * 1e-3
+        grads = rast.backward(params, out, dl)
+        for k in PARAM_NAMES:
+            assert torch.isfinite(grads[k]).all(), k
+    return rast
+
+
+def test_edge_empty_scene():
+    sc = scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)), np.zeros(0), colours=np.zeros((0, 3)))
+    rast = _edge_check(sc, [camera(60.0, 37, 29)])
+    assert rast.required_capacity()[:2] == (0, 0)
+
+
+def test_edge_all_culled_and_degenerate_inputs():
+    sc = scene([[0, 0, -2.0], [0, 0, 0.1], [50, 0, 2.0], [0, 0, 3.0], [0.2, 0, 3.0], [0, 0.1, 4.0]],
+               [[-2.0] * 3, [-2.0] * 3, [-2.0] * 3, [-2.0] * 3, [5.0, -20.0, -3.0], [-20.0] * 3],
+               [[1, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0], [0, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0]],
+               [0.0] * 6, colours=[[0.5] * 3] * 6)
+    _edge_check(sc, [camera(60.0)])
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (37, 29), (17, 100)])
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_edge_ragged_and_tiny_images(wh, ts):
+    w, h = wh
+    rng = np.random.default_rng(w * 131 + h)
+    n = 150
+    means = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(2, 6, n)], 1)
+    q = rng.standard_normal((n, 4))
+    sc = scene(means, rng.normal(-2.5, 0.5, (n, 3)), q, rng.normal(0, 1.5, n), colours=rng.uniform(0, 1, (n, 3)))
+    _edge_check(sc, [camera(40.0, w, h)], ts=ts)
+
+
+def test_edge_screen_filling_gaussians_and_stack():
+    n = 30
+    sc = scene([[0, 0, 3.0 + 0.01 * i] for i in range(n)], [[0.5, 0.4, 0.3]] * n, [[1, 0, 0, 0]] * n,
+               [logit(0.3)] * n, colours=[[0.2 + 0.02 * i, 0.5, 0.7] for i in range(n)])
+    _edge_check(sc, [camera(60.0, 96, 64)])
