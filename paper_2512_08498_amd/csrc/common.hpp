@@ -76,7 +76,7 @@ struct Sizes {
 };
 
 constexpr int kPreBlock = 256;     // Gaussians per preprocess workgroup
-constexpr int kLossBlocks = 1024;  // loss reduction partials
+constexpr int kLossBlocks = 2048;  // loss reduction partials
 
 // Image-model constants (float32 bit patterns written as hex literals).
 constexpr float kNearZ = 0x1.99999ap-3f;       // 0.2

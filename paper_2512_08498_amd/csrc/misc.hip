@@ -9,19 +9,36 @@ namespace gsr {
 
 // loss = sum |img - tgt| / n, dL/dimg = sign(img - tgt) / n.  Per-block
 // partial sums in a fixed order; the last block to finish adds the partials
-// in block order, so the value is deterministic.
+// in block order, so the value is deterministic.  float4 accesses when all
+// three arrays are 16-byte aligned.
 __global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const float *__restrict__ tgt, int64_t n,
                                             float *__restrict__ loss, float *__restrict__ dl,
-                                            float *__restrict__ partials, uint32_t *__restrict__ ticket) {
+                                            float *__restrict__ partials, uint32_t *__restrict__ ticket, int vec) {
   __shared__ float s_red[4];
   __shared__ bool s_last;
   const float inv_n = (float)(1.0 / (double)n);
   float acc = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto sgn = [&](float d) { return d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f); };
+  int64_t tail0 = 0;
+  if (vec) {
+    const int64_t n4 = n / 4;
+    const float4 *a4 = reinterpret_cast<const float4 *>(img);
+    const float4 *b4 = reinterpret_cast<const float4 *>(tgt);
+    float4 *d4 = reinterpret_cast<float4 *>(dl);
+    for (int64_t i = gid; i < n4; i += stride) {
+      const float4 a = a4[i], b = b4[i];
+      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+      acc += (fabsf(dx) + fabsf(dy)) + (fabsf(dz) + fabsf(dw));
+      d4[i] = make_float4(sgn(dx), sgn(dy), sgn(dz), sgn(dw));
+    }
+    tail0 = n4 * 4;
+  }
+  for (int64_t i = tail0 + gid; i < n; i += stride) {
     const float d = img[i] - tgt[i];
     acc += fabsf(d);
-    dl[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+    dl[i] = sgn(d);
   }
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (lane_id() == 0) s_red[wave_id()] = acc;
@@ -32,20 +49,31 @@ __global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const
     s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
   }
   __syncthreads();
-  if (s_last && threadIdx.x == 0) {
+  if (s_last) {
+    // the last block adds the partials: thread t takes blocks t, t+256, ...
+    // in order, then a fixed-shape tree over the threads
     __threadfence();
     double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
       s += (double)__hip_atomic_load(partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *loss = (float)(s / (double)n);
-    *ticket = 0u;
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+    __shared__ double s_d[4];
+    if (lane_id() == 0) s_d[wave_id()] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *loss = (float)(((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)n);
+      *ticket = 0u;
+    }
   }
 }
 
 void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
                uint32_t *ticket, hipStream_t st) {
-  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kLossBlocks));
-  k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, loss, dl, partials, ticket);
+  const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                     reinterpret_cast<uintptr_t>(dl)) & 15u) == 0;
+  const int64_t work = vec ? (n + 3) / 4 : n;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, kLossBlocks));
+  k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, loss, dl, partials, ticket, vec ? 1 : 0);
 }
 
 // One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian.

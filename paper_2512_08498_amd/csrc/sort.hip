@@ -9,7 +9,8 @@
 // chunks, streaming through global memory.
 //
 // Size classes (one workgroup per tile):
-//   n <= 256   : 256 threads x 1 item,  grid over all tiles
+//   n <= 256   :  64 threads x 4 items, grid over all tiles (one wave, so
+//                its barriers are cheap)
 //   n <= 2048  : 256 threads x 8 items, tiles queued by the first kernel
 //   n <= 8192  : 512 threads x 16 items
 //   larger     : 1024 threads, 8192-entry chunks through global memory
@@ -154,8 +155,8 @@ __device__ void sort_tile_lds(SortLds<NT, IPT> &S, const Ws &ws, uint32_t start,
 
 constexpr uint32_t kSmallMax = 256, kMidMax = 2048, kBigMax = 8192;
 
-__global__ __launch_bounds__(256) void k_sort_small(Ws ws, Sizes sz, uint32_t small_max, int force_q) {
-  __shared__ SortLds<256, 1> S;
+__global__ __launch_bounds__(64) void k_sort_small(Ws ws, Sizes sz, uint32_t small_max, int force_q) {
+  __shared__ SortLds<64, 4> S;
   if (ws.scalars[kOverflow]) return;
   const uint32_t tile = blockIdx.x;
   const uint32_t n = ws.tile_count[tile];
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) void k_sort_small(Ws ws, Sizes sz, uint32_t sm
     if (threadIdx.x == 0) ws.tile_recs[start] = (uint32_t)ws.pairs[start];
     return;
   }
-  sort_tile_lds<256, 1>(S, ws, start, n);
+  sort_tile_lds<64, 4>(S, ws, start, n);
 }
 
 template <int NT, int IPT>
@@ -303,7 +304,7 @@ void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t 
                  int force_q, hipStream_t st) {
   (void)views;
   if (sz.t_tot == 0) return;
-  k_sort_small<<<sz.t_tot, 256, 0, st>>>(ws, sz, lds_small_max, force_q);
+  k_sort_small<<<sz.t_tot, 64, 0, st>>>(ws, sz, lds_small_max, force_q);
   k_sort_queue<256, 8><<<1024, 256, 0, st>>>(ws, sz, 0);
   k_sort_queue<512, 16><<<512, 512, 0, st>>>(ws, sz, 1);
   k_sort_huge<<<256, kHugeNT, 0, st>>>(ws, sz);
