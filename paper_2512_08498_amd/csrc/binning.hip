@@ -71,6 +71,28 @@ __global__ void k_tile_abs(const ViewInfo *__restrict__ views, Ws ws, Sizes sz) 
   ws.tile_start[t] += ws.view_pair_base[v];
 }
 
+// Tiles by decreasing list length (1024 buckets of 4 entries; order within
+// a bucket is arbitrary), so the compositing kernels start the longest lists
+// first and the short ones fill in behind them.
+__global__ __launch_bounds__(1024) void k_tile_order(Ws ws, Sizes sz) {
+  constexpr uint32_t NB = 1024;
+  __shared__ uint32_t hist[NB];
+  __shared__ uint32_t s_scan[16];
+  if (ws.scalars[kOverflow]) return;
+  const uint32_t t = threadIdx.x;
+  hist[t] = 0;
+  __syncthreads();
+  auto bucket = [&](uint32_t tile) { return NB - 1 - min(ws.tile_count[tile] >> 2, NB - 1); };
+  for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) atomicAdd(&hist[bucket(i)], 1u);
+  __syncthreads();
+  uint32_t total;
+  const uint32_t base = block_excl_scan<1024>(hist[t], s_scan, total);
+  __syncthreads();
+  hist[t] = base;
+  __syncthreads();
+  for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) ws.tile_order[atomicAdd(&hist[bucket(i)], 1u)] = i;
+}
+
 // Each wave expands 64 consecutive records into their (record, tile) pairs:
 // lane l takes pair b + l of the wave's concatenated tile rectangles, finds
 // its record by a binary search over the wave's prefix sums, and claims a
@@ -128,6 +150,7 @@ void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStr
   k_tile_prefix<<<sz.n_views, 1024, 0, st>>>(views, ws);
   k_view_scan<<<1, 64, 0, st>>>(ws, sz);
   k_tile_abs<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(views, ws, sz);
+  k_tile_order<<<1, 1024, 0, st>>>(ws, sz);
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
   k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz);

@@ -52,7 +52,8 @@ struct Ws {
   uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t *rec_zbits;      // [cap_rec] depth bits
   uint32_t *tile_count;     // [T_tot] list length
-  uint32_t *tile_start;     // [T_tot] list start relative to the view's pair base
+  uint32_t *tile_start;     // [T_tot] list start (absolute after k_tile_abs)
+  uint32_t *tile_order;     // [T_tot] tiles by decreasing list length
   uint32_t *view_pair_base; // [n_views + 1]
   uint32_t *queues;         // [3][T_tot] tiles for the larger sorts
   uint64_t *pairs;          // [cap_pairs] (zbits << 32 | record), bucketed by tile
@@ -89,11 +90,15 @@ constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 0x1.715476p+0f;
 constexpr float kHalfLog2e = 0x1.715476p-1f;   // log2(e) / 2
 
-// Raster payload of one record, four float4:
+// Raster payload of one record, four float4 (64 bytes, read by the
+// compositing kernels through the scalar cache):
 //  p0 = (i0, i1, j0, j1)            inclusive pixel box, as floats
 //  p1 = (offx, offy, qa, qb)        mean offset from the box corner; conic
 //  p2 = (qc, opacity, r, g)         in Cholesky form (see raster.hpp)
-//  p3 = (b, -, -, -)
+//  p3 = (b, i0 | i1 << 16, j0 | j1 << 16, pass)   the box again, as packed
+//                                   16-bit integers, and bits 0..2 set where
+//                                   colour channel ch was not clamped at 0
+//                                   (bit patterns)
 // offx = mu'_x - i0 - 0.5, so dx = (px - i0) - offx is the centre offset of
 // pixel px, exact up to the rounding of offx.
 

@@ -39,8 +39,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
   __shared__ float s_g[B * NW * 9];
   __shared__ uint32_t s_red[NW];
   if (ws.scalars[kOverflow]) return;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= sz.t_tot) return;
+  if (blockIdx.x >= sz.t_tot) return;
+  const uint32_t tile = ws.tile_order[blockIdx.x];  // longest lists first
   const int t = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int v = view_of_tile(views, sz.n_views, tile);
   const ViewInfo vi = views[v];

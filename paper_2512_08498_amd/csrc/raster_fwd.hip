@@ -4,8 +4,7 @@
 //
 // Records are staged in LDS in batches of NT (one per thread, four float4
 // each, stored as four arrays so all lanes read the same address: LDS
-// broadcast).  A lane reads the rest of a record only if one of its pixels
-// lies in the record's box.  Per pixel the kernel keeps T, the colour and the position one
+// broadcast).  Per pixel the kernel keeps T, the colour and the position one
 // past the last composited entry, which the backward pass starts from.
 #include "kernels.hpp"
 #include "raster.hpp"
@@ -14,16 +13,16 @@
 namespace gsr {
 
 template <int TS>
-__global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_fwd(const ViewInfo *__restrict__ views, Ws ws,
+__global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *__restrict__ views, Ws ws,
                                                                 Sizes sz, float *__restrict__ image,
                                                                 float *__restrict__ t_final,
                                                                 uint32_t *__restrict__ last_pos,
                                                                 uint32_t *__restrict__ n_contrib) {
-  constexpr int NT = TileCfg<TS>::NT, PPT = TileCfg<TS>::PPT, B = NT;
+  constexpr int NT = FwdTile<TS>::NT, PPT = FwdTile<TS>::PPT, B = NT;
   __shared__ float4 s_p0[B], s_p1[B], s_p2[B], s_p3[B];
   if (ws.scalars[kOverflow]) return;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= sz.t_tot) return;
+  if (blockIdx.x >= sz.t_tot) return;
+  const uint32_t tile = ws.tile_order[blockIdx.x];
   const int t = threadIdx.x;
   const int v = view_of_tile(views, sz.n_views, tile);
   const ViewInfo vi = views[v];
@@ -39,7 +38,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_fwd(const ViewInfo *
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     int x, y;
-    pixel_of<TS>(t, p, x, y);
+    fwd_pixel<TS>(t, p, x, y);
     px[p] = tx * TS + x;
     py[p] = ty * TS + y;
     fx[p] = (float)px[p];
@@ -51,24 +50,6 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_fwd(const ViewInfo *
     cnt[p] = 0;
   }
 
-  // the next batch's records are fetched into registers while the current
-  // batch is composited
-  float4 f0, f1, f2, f3;
-  auto fetch = [&](uint32_t b0) {
-    if ((uint32_t)t < min((uint32_t)B, n - b0)) {
-      uint32_t rec = ws.tile_recs[start + b0 + t];
-      if (rec >= nrec) {  // corrupt list: flag it, stay in bounds
-        ws.scalars[kOverflow] = 4u;
-        rec = 0;
-      }
-      const float4 *src = ws.rec_payload + (size_t)rec * 4;
-      f0 = src[0];
-      f1 = src[1];
-      f2 = src[2];
-      f3 = src[3];
-    }
-  };
-  if (n > 0) fetch(0);
   for (uint32_t b0 = 0; b0 < n; b0 += B) {
     int alive = 0;
 #pragma unroll
@@ -76,28 +57,25 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_fwd(const ViewInfo *
     if (!__syncthreads_or(alive)) break;
     const uint32_t m = min((uint32_t)B, n - b0);
     if ((uint32_t)t < m) {
-      s_p0[t] = f0;
-      s_p1[t] = f1;
-      s_p2[t] = f2;
-      s_p3[t] = f3;
+      uint32_t rec = ws.tile_recs[start + b0 + t];
+      if (rec >= nrec) {  // corrupt list: flag it, stay in bounds
+        ws.scalars[kOverflow] = 4u;
+        rec = 0;
+      }
+      const float4 *src = ws.rec_payload + (size_t)rec * 4;
+      s_p0[t] = src[0];
+      s_p1[t] = src[1];
+      s_p2[t] = src[2];
+      s_p3[t] = src[3];
     }
     __syncthreads();
-    if (b0 + B < n) fetch(b0 + B);
     for (uint32_t j = 0; j < m; ++j) {
       const float4 box = s_p0[j];
-      bool in[PPT];
-      bool any_in = false;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        in[p] = !done[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w;
-        any_in |= in[p];
-      }
-      if (!any_in) continue;
-      const float4 q1 = s_p1[j], q2 = s_p2[j];
-      const float cb = s_p3[j].x;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (in[p]) {
+        const bool in = !done[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w;
+        if (in) {
+          const float4 q1 = s_p1[j], q2 = s_p2[j];
           const float dx = (fx[p] - box.x) - q1.x;
           const float dy = (fy[p] - box.z) - q1.y;
           const float u = fmaf(q1.w, dy, dx);
@@ -109,9 +87,10 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_fwd(const ViewInfo *
               done[p] = true;
             } else {
               const float w = alpha * T[p];
+              const float b = s_p3[j].x;
               C0[p] = fmaf(w, q2.z, C0[p]);
               C1[p] = fmaf(w, q2.w, C1[p]);
-              C2[p] = fmaf(w, cb, C2[p]);
+              C2[p] = fmaf(w, b, C2[p]);
               T[p] = tn;
               last[p] = b0 + j + 1;
               cnt[p] += 1;
@@ -144,13 +123,13 @@ void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, flo
   if (grid == 0) return;
   switch (sz.ts) {
     case 8:
-      k_raster_fwd<8><<<grid, TileCfg<8>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd<8><<<grid, FwdTile<8>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
       break;
     case 32:
-      k_raster_fwd<32><<<grid, TileCfg<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd<32><<<grid, FwdTile<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
       break;
     default:
-      k_raster_fwd<16><<<grid, TileCfg<16>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd<16><<<grid, FwdTile<16>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
       break;
   }
 }

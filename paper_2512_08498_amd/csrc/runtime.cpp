@@ -19,7 +19,7 @@ namespace {
 struct Layout {
   size_t scalars, diff, cursor, zero_end;
   size_t block_sums, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
-  size_t tile_count, tile_start, vbase, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
+  size_t tile_count, tile_start, tile_order, vbase, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
   size_t total;
 };
 
@@ -105,6 +105,7 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   w.rec_zbits = reinterpret_cast<uint32_t *>(b + L.rec_zbits);
   w.tile_count = reinterpret_cast<uint32_t *>(b + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t *>(b + L.tile_start);
+  w.tile_order = reinterpret_cast<uint32_t *>(b + L.tile_order);
   w.view_pair_base = reinterpret_cast<uint32_t *>(b + L.vbase);
   w.queues = reinterpret_cast<uint32_t *>(b + L.queues);
   w.pairs = reinterpret_cast<uint64_t *>(b + L.pairs);
@@ -137,6 +138,7 @@ Layout make_layout(const Sizes &s, uint32_t diff_words, int32_t n_views) {
   put(L.rec_zbits, (size_t)s.cap_rec * 4);
   put(L.tile_count, (size_t)s.t_tot * 4);
   put(L.tile_start, (size_t)s.t_tot * 4);
+  put(L.tile_order, (size_t)s.t_tot * 4);
   put(L.vbase, (size_t)(n_views + 1) * 4);
   put(L.queues, (size_t)s.t_tot * 12);
   put(L.pairs, (size_t)s.cap_pairs * 8);
