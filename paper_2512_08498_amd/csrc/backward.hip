@@ -34,10 +34,32 @@ __device__ __forceinline__ void bias_corrections(const AdamArgs &a, float &bc1, 
   bc2 = 1.0f - exp2f(t * log2f(a.beta2));
 }
 
+// Colour cotangent of record r: dL/drgb where the channel was not clamped.
+__device__ __forceinline__ void colour_cot(const Ws &ws, uint32_t r, float c[3]) {
+  const float4 gb = ws.g2d[(size_t)r * 3 + 1], gc = ws.g2d[(size_t)r * 3 + 2];
+  const uint32_t pass = __float_as_uint(ws.rec_payload[(size_t)r * 4 + 3].w);
+  c[0] = (pass & 1u) ? gb.z : 0.0f;
+  c[1] = (pass & 2u) ? gb.w : 0.0f;
+  c[2] = (pass & 4u) ? gc.x : 0.0f;
+}
+
+// Unit direction from the camera centre -R^T t to the mean, and 1/|mean - C|.
+__device__ __forceinline__ void view_dir(const Cam &c, const float m3[3], float d[3], float &inv) {
+  const float cxw = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+  const float cyw = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+  const float czw = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+  const float ex = m3[0] - cxw, ey = m3[1] - cyw, ez = m3[2] - czw;
+  inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+  d[0] = ex * inv;
+  d[1] = ey * inv;
+  d[2] = ez * inv;
+}
+
 template <int DEG, bool ADAM>
 __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__restrict__ cams, Ws ws, Sizes sz,
                                                   MutPtrs grads, int accumulate, AdamArgs adam) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int KC = 4;  // SH coefficients per chunk of the second pass
   if (ws.scalars[kOverflow]) return;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sz.n) return;
@@ -46,53 +68,39 @@ __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__rest
   load_gaussian(gp.mean, gp.log_scale, gp.quat, n, g, m3, l3, q4);
   float d_mean[3] = {0.f, 0.f, 0.f}, d_s[3] = {0.f, 0.f, 0.f}, d_op = 0.f;
   float d_rq[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-  float d_sh[K][3];
-#pragma unroll
-  for (int k = 0; k < K; ++k) d_sh[k][0] = d_sh[k][1] = d_sh[k][2] = 0.f;
   Proj P;
   bool seen = false;
   const uint32_t r0 = ws.rec_start[g], r1 = ws.rec_start[g + 1];
+
+  // pass 1: geometry, opacity, and the colour's dependence on the direction
   for (uint32_t r = r0; r < r1; ++r) {
     const int v = (int)ws.rec_view[r];
     const Cam c = load_cam(cams, v);
     project_spec(m3, l3, q4, c, P);
     seen = true;
-    const float4 ga = ws.g2d[(size_t)r * 3 + 0], gb = ws.g2d[(size_t)r * 3 + 1], gc = ws.g2d[(size_t)r * 3 + 2];
+    const float4 ga = ws.g2d[(size_t)r * 3 + 0], gb = ws.g2d[(size_t)r * 3 + 1];
     const float d_offx = ga.x, d_offy = ga.y, d_qa = ga.z, d_qb = ga.w, d_qc = gb.x;
     d_op += gb.y;
-    const float d_rgb[3] = {gb.z, gb.w, gc.x};
 
-    // colour -> SH coefficients and viewing direction
-    const float cxw = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
-    const float cyw = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
-    const float czw = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
-    const float ex = m3[0] - cxw, ey = m3[1] - cyw, ez = m3[2] - czw;
-    const float inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
-    const float dx = ex * inv, dy = ey * inv, dz = ez * inv;
-    float Y[16];
-    sh_basis(dx, dy, dz, DEG, Y);
-    float w[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) w[k] = 0.f;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float s = 0.5f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s += gp.sh[((int64_t)k * 3 + ch) * n + g] * Y[k];
-      const float gch = s >= 0.0f ? d_rgb[ch] : 0.0f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        d_sh[k][ch] += Y[k] * gch;
-        w[k] += gch * gp.sh[((int64_t)k * 3 + ch) * n + g];
-      }
-    }
     if (DEG > 0) {
+      float cc[3], d[3], inv;
+      colour_cot(ws, r, cc);
+      view_dir(c, m3, d, inv);
+      float w[16];
+      w[0] = 0.0f;
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        const int64_t base = (int64_t)k * 3 * n + g;
+        w[k] = cc[0] * gp.sh[base] + cc[1] * gp.sh[base + n] + cc[2] * gp.sh[base + 2 * n];
+      }
+#pragma unroll
+      for (int k = K; k < 16; ++k) w[k] = 0.0f;
       float gd[3];
-      sh_grad_dot(dx, dy, dz, DEG, w, gd);
-      const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
-      d_mean[0] += (gd[0] - dot * dx) * inv;
-      d_mean[1] += (gd[1] - dot * dy) * inv;
-      d_mean[2] += (gd[2] - dot * dz) * inv;
+      sh_grad_dot(d[0], d[1], d[2], DEG, w, gd);
+      const float dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+      d_mean[0] += (gd[0] - dot * d[0]) * inv;
+      d_mean[1] += (gd[1] - dot * d[1]) * inv;
+      d_mean[2] += (gd[2] - dot * d[2]) * inv;
     }
 
     // conic (Cholesky form) -> 2D covariance
@@ -188,48 +196,63 @@ __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__rest
   const float op = 1.0f / (1.0f + expf(-theta));
   const float d_theta = op * (1.0f - op) * d_op;
 
-  if (!ADAM) {
-    auto put = [&](float *dst, int64_t idx, float val) { dst[idx] = accumulate ? dst[idx] + val : val; };
+  float bc1 = 1.0f, bc2 = 1.0f;
+  if (ADAM) bias_corrections(adam, bc1, bc2);
+  // write a gradient, or apply the Adam update to its parameter
+  auto emit = [&](float *p, float *m, float *v, float *gout, int64_t idx, float gval, float lr) {
+    if (!ADAM) {
+      gout[idx] = accumulate ? gout[idx] + gval : gval;
+      return;
+    }
+    float pp = p[idx], mm = m[idx], vv = v[idx];
+    adam_update(pp, mm, vv, gval, lr, adam.beta1, adam.beta2, adam.eps, bc1, bc2);
+    p[idx] = pp;
+    m[idx] = mm;
+    v[idx] = vv;
+    if (gout) gout[idx] = gval;
+  };
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      put(grads.mean, k * n + g, d_mean[k]);
-      put(grads.log_scale, k * n + g, d_l[k]);
+  for (int k = 0; k < 3; ++k) {
+    emit(adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, k * n + g, d_mean[k], adam.lr[0]);
+    emit(adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, k * n + g, d_l[k], adam.lr[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) emit(adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, k * n + g, d_q[k], adam.lr[2]);
+  emit(adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit, g, d_theta,
+       adam.lr[3]);
+
+  // pass 2: SH coefficients, KC at a time (bounds the live registers)
+#pragma unroll
+  for (int kc = 0; kc < K; kc += KC) {
+    float a[KC][3];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) a[kk][0] = a[kk][1] = a[kk][2] = 0.0f;
+    for (uint32_t r = r0; r < r1; ++r) {
+      const Cam c = load_cam(cams, (int)ws.rec_view[r]);
+      float cc[3], d[3], inv;
+      colour_cot(ws, r, cc);
+      view_dir(c, m3, d, inv);
+      float Y[16];
+      sh_basis(d[0], d[1], d[2], DEG, Y);
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        if (kc + kk < K) {
+          a[kk][0] += Y[kc + kk] * cc[0];
+          a[kk][1] += Y[kc + kk] * cc[1];
+          a[kk][2] += Y[kc + kk] * cc[2];
+        }
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) put(grads.quat, k * n + g, d_q[k]);
-    put(grads.opacity_logit, g, d_theta);
+    for (int kk = 0; kk < KC; ++kk) {
+      if (kc + kk < K) {
+        const int k = kc + kk;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) put(grads.sh, ((int64_t)k * 3 + ch) * n + g, d_sh[k][ch]);
-  } else {
-    float bc1, bc2;
-    bias_corrections(adam, bc1, bc2);
-    const float b1 = adam.beta1, b2 = adam.beta2, eps = adam.eps;
-    auto upd = [&](float *p, float *m, float *v, float *gout, int64_t idx, float gval, float lr) {
-      float pp = p[idx], mm = m[idx], vv = v[idx];
-      adam_update(pp, mm, vv, gval, lr, b1, b2, eps, bc1, bc2);
-      p[idx] = pp;
-      m[idx] = mm;
-      v[idx] = vv;
-      if (gout) gout[idx] = gval;
-    };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      upd(adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, k * n + g, d_mean[k], adam.lr[0]);
-      upd(adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, k * n + g, d_l[k], adam.lr[1]);
+        for (int ch = 0; ch < 3; ++ch)
+          emit(adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, ((int64_t)k * 3 + ch) * n + g, a[kk][ch],
+               k == 0 ? adam.lr[4] : adam.lr[5]);
+      }
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      upd(adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, k * n + g, d_q[k], adam.lr[2]);
-    upd(adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit, g, d_theta,
-        adam.lr[3]);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch)
-        upd(adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, ((int64_t)k * 3 + ch) * n + g, d_sh[k][ch],
-            k == 0 ? adam.lr[4] : adam.lr[5]);
   }
 }
 

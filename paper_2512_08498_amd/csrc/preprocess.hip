@@ -153,18 +153,22 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
     float Y[16];
     sh_basis(dx * inv, dy * inv, dz * inv, DEG, Y);
     float rgb[3];
+    uint32_t pass = 0;  // bit ch: colour channel ch not clamped (gradient passes)
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float s = 0.5f;
 #pragma unroll
       for (int k = 0; k < K; ++k) s += sh[k][ch] * Y[k];
       rgb[ch] = fmaxf(s, 0.0f);
+      pass |= (s >= 0.0f ? 1u : 0u) << ch;
     }
     const ViewInfo vi = views[v];
     ws.rec_payload[(size_t)rec * 4 + 0] = make_float4((float)P.i0, (float)P.i1, (float)P.j0, (float)P.j1);
     ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
     ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
-    ws.rec_payload[(size_t)rec * 4 + 3] = make_float4(rgb[2], 0.0f, 0.0f, 0.0f);
+    ws.rec_payload[(size_t)rec * 4 + 3] =
+        make_float4(rgb[2], __uint_as_float((uint32_t)P.i0 | ((uint32_t)P.i1 << 16)),
+                    __uint_as_float((uint32_t)P.j0 | ((uint32_t)P.j1 << 16)), __uint_as_float(pass));
     const int tx0 = P.i0 >> ts_shift, tx1 = P.i1 >> ts_shift;
     const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
     ws.rec_g[rec] = (uint32_t)g;
