@@ -74,7 +74,7 @@ __global__ void k_tile_abs(const ViewInfo *__restrict__ views, Ws ws, Sizes sz) 
 // Tiles by decreasing list length (1024 buckets of 4 entries; order within
 // a bucket is arbitrary), so the compositing kernels start the longest lists
 // first and the short ones fill in behind them.
-__global__ __launch_bounds__(1024) void k_tile_order(Ws ws, Sizes sz) {
+__global__ __launch_bounds__(1024) void k_tile_order(Ws ws, Sizes sz, uint32_t long_list) {
   constexpr uint32_t NB = 1024;
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t s_scan[16];
@@ -91,6 +91,13 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws, Sizes sz) {
   hist[t] = base;
   __syncthreads();
   for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) ws.tile_order[atomicAdd(&hist[bucket(i)], 1u)] = i;
+  // tiles with at least long_list entries come first (long_list is a
+  // multiple of the bucket width); the backward splits them over four waves
+  uint32_t nl = 0;
+  for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) nl += ws.tile_count[i] >= long_list ? 1u : 0u;
+  uint32_t tot_long;
+  block_excl_scan<1024>(nl, s_scan, tot_long);
+  if (t == 0) ws.scalars[kNumLong] = tot_long;
 }
 
 // Each wave expands 64 consecutive records into their (record, tile) pairs:
@@ -150,7 +157,7 @@ void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStr
   k_tile_prefix<<<sz.n_views, 1024, 0, st>>>(views, ws);
   k_view_scan<<<1, 64, 0, st>>>(ws, sz);
   k_tile_abs<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(views, ws, sz);
-  k_tile_order<<<1, 1024, 0, st>>>(ws, sz);
+  k_tile_order<<<1, 1024, 0, st>>>(ws, sz, 512u);
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
   k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz);

@@ -35,6 +35,7 @@ enum Scalar : int {
   kQueueBig = 4,      // tiles queued for the 8192-entry LDS sort
   kQueueHuge = 5,     // tiles queued for the global-memory radix sort
   kLossTicket = 6,    // loss reduction: blocks done
+  kNumLong = 7,       // 16 px tiles with a long list (a prefix of tile_order)
   kNumScalars = 16
 };
 

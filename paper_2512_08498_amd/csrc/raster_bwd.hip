@@ -27,21 +27,49 @@ namespace gsr {
 
 constexpr float kLn2 = 0x1.62e43p-1f;
 
-template <int TS>
-__global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *__restrict__ views, Ws ws,
-                                                                Sizes sz, const float *__restrict__ t_final,
-                                                                const uint32_t *__restrict__ last_pos,
-                                                                const float *__restrict__ dL_dimage) {
-  constexpr int NT = TileCfg<TS>::NT, PPT = TileCfg<TS>::PPT, NW = TileCfg<TS>::NW;
-  constexpr int B = NT >= 128 ? 128 : NT;
-  __shared__ float4 s_p0[B], s_p1[B], s_p2[B], s_p3[B];
-  __shared__ uint32_t s_out[B];
-  __shared__ float s_g[B * NW * 9];
-  __shared__ uint32_t s_red[NW];
-  if (ws.scalars[kOverflow]) return;
-  if (blockIdx.x >= sz.t_tot) return;
-  const uint32_t tile = ws.tile_order[blockIdx.x];  // longest lists first
-  const int t = threadIdx.x, lane = lane_id(), wv = wave_id();
+// Barrier over the threads that share one tile's LDS: the workgroup, or a
+// single wave (whose LDS accesses are performed in order).
+template <bool WG>
+__device__ __forceinline__ void group_sync() {
+  if (WG) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <bool WG>
+__device__ __forceinline__ uint32_t group_max(uint32_t x, uint32_t *red) {
+  x = wave_reduce_max(x);
+  if (!WG) return __builtin_amdgcn_readfirstlane(x);
+  if (lane_id() == 0) red[wave_id()] = x;
+  __syncthreads();
+  uint32_t m = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, red[w]);
+  return m;
+}
+
+// LDS of one tile walk: a batch of B records' payloads, their partials
+// slots and the per-wave gradient sums.
+template <int B, int NW>
+struct BwdLds {
+  float4 p0[B], p1[B], p2[B], p3[B];
+  uint32_t out[B];
+  float g[B * NW * 9];
+  uint32_t red[4];
+};
+
+// The adjoint walk over one tile's list by a group of NT threads (a
+// workgroup when WG, else one wave), each thread holding PPT pixels given by
+// `pix(t, p, x, y)` relative to the tile origin.
+template <int TS, int NT, int PPT, bool WG, int B, class Pix>
+__device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, const Ws &ws, const Sizes &sz,
+                                         uint32_t tile, int t, BwdLds<B, NT / kWave> &L,
+                                         const float *__restrict__ t_final, const uint32_t *__restrict__ last_pos,
+                                         const float *__restrict__ dL_dimage, Pix pix) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id(), wv = t / kWave;
   const int v = view_of_tile(views, sz.n_views, tile);
   const ViewInfo vi = views[v];
   const uint32_t lt = tile - vi.tile_base;
@@ -57,7 +85,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     int x, y;
-    pixel_of<TS>(t, p, x, y);
+    pix(t, p, x, y);
     const int px = (int)tx * TS + x, py = (int)ty * TS + y;
     fx[p] = (float)px;
     fy[p] = (float)py;
@@ -65,13 +93,13 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
     R1[p] = sz.bg[1];
     R2[p] = sz.bg[2];
     if (px < vi.w && py < vi.h) {
-      const uint32_t pix = (uint32_t)py * (uint32_t)vi.w + (uint32_t)px;
-      T[p] = t_final[vi.pix_off + pix];
-      last[p] = last_pos[vi.pix_off + pix];
+      const uint32_t pixi = (uint32_t)py * (uint32_t)vi.w + (uint32_t)px;
+      T[p] = t_final[vi.pix_off + pixi];
+      last[p] = last_pos[vi.pix_off + pixi];
       const float *gi = dL_dimage + (size_t)3 * vi.pix_off;
-      g0[p] = gi[pix];
-      g1[p] = gi[hw + pix];
-      g2[p] = gi[2 * hw + pix];
+      g0[p] = gi[pixi];
+      g1[p] = gi[hw + pixi];
+      g2[p] = gi[2 * hw + pixi];
     } else {
       T[p] = 1.0f;
       last[p] = 0;
@@ -79,12 +107,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
     }
     my_max = max(my_max, last[p]);
   }
-  my_max = wave_reduce_max(my_max);
-  if (lane == 0) s_red[wv] = my_max;
-  __syncthreads();
-  uint32_t max_last = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) max_last = max(max_last, s_red[w]);
+  const uint32_t max_last = group_max<WG>(my_max, L.red);
 
   // slot of this tile's pair in the record-major partials array
   auto pair_slot = [&](uint32_t rec) {
@@ -93,7 +116,11 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
       rec = 0;
     }
     const uint2 rc = ws.rec_rect[rec];
-    const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu;
+    const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+    if (tx < tx0 || tx > tx1 || ty < ty0 || ty > ty1) {  // not this record's tile: corrupt list
+      ws.scalars[kOverflow] = 4u;
+      return ws.rec_pairoff[rec];
+    }
     return ws.rec_pairoff[rec] + (ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
   };
   const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -121,7 +148,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
       f3 = src[3];
     }
   };
-  auto batch_lo = [&](uint32_t hi) { return hi > (uint32_t)B ? hi - B : 0u; };
+  auto batch_lo = [](uint32_t hi) { return hi > (uint32_t)B ? hi - B : 0u; };
   if (max_last > 0) {
     const uint32_t lo0 = batch_lo(max_last);
     if ((uint32_t)t < max_last - lo0) fetch(lo0);
@@ -129,23 +156,23 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
   for (uint32_t hi = max_last; hi > 0;) {
     const uint32_t lo = batch_lo(hi);
     const uint32_t m = hi - lo;
-    __syncthreads();
+    group_sync<WG>();
     if ((uint32_t)t < m) {
-      s_p0[t] = f0;
-      s_p1[t] = f1;
-      s_p2[t] = f2;
-      s_p3[t] = f3;
-      s_out[t] = fslot;
+      L.p0[t] = f0;
+      L.p1[t] = f1;
+      L.p2[t] = f2;
+      L.p3[t] = f3;
+      L.out[t] = fslot;
     }
     if (lo > 0) {
       const uint32_t lo2 = batch_lo(lo);
       if ((uint32_t)t < lo - lo2) fetch(lo2);
     }
-    for (int k = t; k < B * NW * 9; k += NT) s_g[k] = 0.0f;
-    __syncthreads();
+    for (int k = t; k < B * NW * 9; k += NT) L.g[k] = 0.0f;
+    group_sync<WG>();
     for (int jj = (int)m - 1; jj >= 0; --jj) {
       const uint32_t pos = lo + (uint32_t)jj;
-      const float4 box = s_p0[jj];
+      const float4 box = L.p0[jj];
       bool in[PPT];
       bool any_in = false;
 #pragma unroll
@@ -159,8 +186,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
             a_b = 0.f;
       bool any = false;
       if (any_in) {
-        const float4 q1 = s_p1[jj], q2 = s_p2[jj];
-        const float cb = s_p3[jj].x;
+        const float4 q1 = L.p1[jj], q2 = L.p2[jj];
+        const float cb = L.p3[jj].x;
         const float two_qa = 2.0f * q1.z, two_qc = 2.0f * q2.x;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
@@ -207,13 +234,13 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
         const float r6 = wave_sum_to_lane63(a_r), r7 = wave_sum_to_lane63(a_g);
         const float r8 = wave_sum_to_lane63(a_b);
         if (lane == kWave - 1) {
-          float *dst = s_g + ((size_t)jj * NW + wv) * 9;
+          float *dst = L.g + ((size_t)jj * NW + wv) * 9;
           dst[0] = r0 * kLn2; dst[1] = r1 * kLn2; dst[2] = r2 * kLn2; dst[3] = r3 * kLn2;
           dst[4] = r4 * kLn2; dst[5] = r5; dst[6] = r6; dst[7] = r7; dst[8] = r8;
         }
       }
     }
-    __syncthreads();
+    group_sync<WG>();
     for (uint32_t e = t; e < m; e += NT) {
       float s9[9];
 #pragma unroll
@@ -221,14 +248,74 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
 #pragma unroll
       for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) s9[c] += s_g[((size_t)e * NW + w) * 9 + c];
-      const uint32_t slot = s_out[e];
+        for (int c = 0; c < 9; ++c) s9[c] += L.g[((size_t)e * NW + w) * 9 + c];
+      const uint32_t slot = L.out[e];
       ws.partials[(size_t)slot * 3 + 0] = make_float4(s9[0], s9[1], s9[2], s9[3]);
       ws.partials[(size_t)slot * 3 + 1] = make_float4(s9[4], s9[5], s9[6], s9[7]);
       ws.partials[(size_t)slot * 3 + 2] = make_float4(s9[8], 0.0f, 0.0f, 0.0f);
     }
     hi = lo;
   }
+}
+
+// 16 px tiles.  Tiles whose list has at least kLongList entries (a prefix
+// of the longest-first order) take a whole workgroup: four waves, each an
+// 8 x 8 quadrant with one pixel per lane, sharing 128-record LDS batches,
+// so a long list is walked four times faster.  The remaining tiles are
+// packed four to a workgroup, one wave each (16 x 16 pixels, four per lane),
+// so each record's wave reduction is paid once per tile; neighbours in the
+// longest-first order have similar lengths, so the four waves finish
+// together.
+constexpr uint32_t kLongList = 512;
+
+union BwdLds16 {
+  BwdLds<128, 4> quad;
+  BwdLds<64, 1> wave[4];
+};
+
+__global__ __launch_bounds__(256) void k_raster_bwd16(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
+                                                      const float *__restrict__ t_final,
+                                                      const uint32_t *__restrict__ last_pos,
+                                                      const float *__restrict__ dL_dimage) {
+  __shared__ BwdLds16 S;
+  if (ws.scalars[kOverflow]) return;
+  const uint32_t n_long = ws.scalars[kNumLong];
+  const int t = threadIdx.x;
+  if (blockIdx.x < n_long) {
+    const uint32_t tile = ws.tile_order[blockIdx.x];
+    bwd_walk<16, 256, 1, true, 128>(views, ws, sz, tile, t, S.quad, t_final, last_pos, dL_dimage,
+                                    [](int tt, int, int &x, int &y) {
+                                      const int l = tt & 63, w = tt >> 6;
+                                      x = (w & 1) * 8 + (l & 7);
+                                      y = (w >> 1) * 8 + (l >> 3);
+                                    });
+  } else {
+    const uint32_t i = n_long + (blockIdx.x - n_long) * 4u + (uint32_t)wave_id();
+    if (i >= sz.t_tot) return;
+    const uint32_t tile = ws.tile_order[i];
+    bwd_walk<16, 64, 4, false, 64>(views, ws, sz, tile, lane_id(), S.wave[wave_id()], t_final, last_pos,
+                                   dL_dimage, [](int tt, int p, int &x, int &y) {
+                                     x = (tt & 7) + (p & 1) * 8;
+                                     y = (tt >> 3) + (p >> 1) * 8;
+                                   });
+  }
+}
+
+// 8 and 32 px tiles: one workgroup per tile (one wave at 8 px with one pixel
+// per lane; four waves at 32 px, one 16 x 16 quadrant each).
+template <int TS>
+__global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *__restrict__ views, Ws ws,
+                                                                Sizes sz, const float *__restrict__ t_final,
+                                                                const uint32_t *__restrict__ last_pos,
+                                                                const float *__restrict__ dL_dimage) {
+  constexpr int NT = TileCfg<TS>::NT, PPT = TileCfg<TS>::PPT;
+  constexpr int B = NT >= 128 ? 128 : NT;
+  __shared__ BwdLds<B, NT / kWave> S;
+  if (ws.scalars[kOverflow]) return;
+  if (blockIdx.x >= sz.t_tot) return;
+  const uint32_t tile = ws.tile_order[blockIdx.x];  // longest lists first
+  bwd_walk<TS, NT, PPT, true, B>(views, ws, sz, tile, threadIdx.x, S, t_final, last_pos, dL_dimage,
+                                 [](int tt, int p, int &x, int &y) { pixel_of<TS>(tt, p, x, y); });
 }
 
 // Sum each record's per-tile partials (contiguous, record-major) into its
@@ -294,19 +381,18 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws) {
 
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st) {
-  const uint32_t grid = tile_grid(sz.t_tot);
-  if (grid > 0) {
-    switch (sz.ts) {
-      case 8:
-        k_raster_bwd<8><<<grid, TileCfg<8>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-        break;
-      case 32:
-        k_raster_bwd<32><<<grid, TileCfg<32>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-        break;
-      default:
-        k_raster_bwd<16><<<grid, TileCfg<16>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-        break;
-    }
+  if (sz.t_tot == 0) return;
+  switch (sz.ts) {
+    case 8:
+      k_raster_bwd<8><<<sz.t_tot, TileCfg<8>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
+      break;
+    case 32:
+      k_raster_bwd<32><<<sz.t_tot, TileCfg<32>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
+      break;
+    default:
+      // at most t_tot workgroups: one per long tile, then one per four tiles
+      k_raster_bwd16<<<sz.t_tot, 256, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
+      break;
   }
 }
 
