@@ -39,30 +39,77 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stage, n, k_sh, views, px, rec, pairs, fused_adam=True):
-    """Bytes each stage must move at least once (see the design notes):
-    parameters read, records / pairs written and read, images, Adam state."""
-    pg = 11 + 3 * k_sh  # parameters per Gaussian
-    if stage == "preprocess":
-        return 4 * pg * n + 64 * rec + 24 * rec          # params in; payload + meta out
-    if stage == "binning":
-        return 24 * rec + 8 * pairs                       # meta in; entries out
-    if stage == "sort":
-        return 8 * pairs + 4 * pairs                      # entries in; sorted records out
-    if stage == "raster_fwd":
-        return 4 * pairs + 64 * rec + 24 * px             # lists + payload in; image, T, last, count out
-    if stage == "loss":
-        return 36 * px                                    # image + target in; gradient out
-    if stage == "raster_bwd":
-        return 4 * pairs + 64 * rec + 20 * px + 36 * pairs  # lists, payload, dL/dC, T, last in; partials out
-    if stage == "reduce":
-        return 36 * pairs + 36 * rec
-    if stage == "pre_bwd":
-        b = 4 * (pg * n) + 36 * rec                       # params + record grads in
-        return b + (24 * pg * n if fused_adam else 4 * pg * n)  # Adam: m, v in/out, p out
-    if stage == "adam":
-        return 28 * pg * n
-    return 0
+# Lane operations of one (pixel, Gaussian) evaluation, counted from the
+# formulas (each add, mul, fma, min, compare, exp2 and rcp is one op; loads,
+# control flow and the per-record wave reductions are not counted):
+#   forward : box test 4, offsets 4, u 1, q 4, exp2 1, opacity and cap 2,
+#             alpha test 1, T update 2, stop test 1, weight 1, colour 3  = 24
+#   backward: the above up to alpha (box 4 + in-front test 1, 13), rcp and
+#             T recovery 3, weight 1, colour grads 3, suffix differences 3,
+#             dL/dalpha 4, suffix update 3, cap test 1, opacity grad 1,
+#             dq 1, conic grads 5, offset grads 5                        = 48
+FWD_OPS_PER_EVAL = 24
+BWD_OPS_PER_EVAL = 48
+
+
+def stage_work(stage, n, n_u, pg, views, px, rec, pairs, tiles, evals):
+    """(algorithmic HBM bytes, algorithmic lane ops) of one stage: every array
+    the method needs read or written once (ideal one-pass sort, Adam state
+    read and written once), and the compositing evaluations."""
+    if stage == "preprocess":   # params in (visible ones whole), records out; visibility scan
+        return 12 * n + 4 * (pg - 3) * n_u + 4 * views * n + 48 * rec + 8 * views * n, 0
+    if stage == "binning":      # records in; (key, value) pairs out
+        return 24 * rec + 12 * pairs, 0
+    if stage == "sort":         # pairs in and out; tile ranges
+        return 24 * pairs + 8 * pairs + 8 * tiles, 0
+    if stage == "raster_fwd":   # lists + records in; image, T, last, count out
+        return 40 * pairs + 20 * px, FWD_OPS_PER_EVAL * evals
+    if stage == "loss":         # image + target in; gradient out
+        return 36 * px, 0
+    if stage == "raster_bwd":   # lists, records, dL/dC, T, last in
+        return 40 * pairs + 20 * px, BWD_OPS_PER_EVAL * evals
+    if stage == "reduce":       # per-record 2D gradients out and back in
+        return 72 * rec, 0
+    if stage == "pre_bwd":      # 2D grads + params in; Adam p, m, v in and out
+        return 36 * rec + 4 * pg * (n_u + n) + 28 * pg * n, 0
+    return 0, 0
+
+
+STEP_STAGES = ("preprocess", "binning", "sort", "raster_fwd", "loss", "raster_bwd", "reduce", "pre_bwd")
+STAGE_KERNEL = {"raster_bwd": "k_raster_bwd16", "raster_fwd": "k_raster_fwd<16>", "preprocess": "k_pre_write<3>",
+                "pre_bwd": "k_pre_bwd<3,true>"}
+
+
+def source_hash(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# HBM traffic of a kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# recorded under profiles/ with the hash of the kernel's sources; reported
+# only while the sources are unchanged.
+TRAFFIC_SOURCES = {"k_raster_bwd16": ["paper_2512_08498_amd/csrc/raster_bwd.hip", "paper_2512_08498_amd/csrc/raster.hpp",
+                                      "paper_2512_08498_amd/csrc/util.hpp", "paper_2512_08498_amd/csrc/common.hpp"]}
+
+
+def recorded_traffic(kernel, workload):
+    import re
+
+    srcs = TRAFFIC_SOURCES.get(kernel)
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not srcs or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_h = re.search(r"source hash: `([0-9a-f]+)`", text)
+    m_b = re.search(r"HBM bytes per launch: ([0-9.e+]+)", text)
+    if not m_h or not m_b or m_h.group(1) != source_hash(srcs):
+        return None
+    return float(m_b.group(1))
 
 
 def cpu_baseline(scene, cams, targets, total_px, budget_s=15.0, win=32, seed=3003):
@@ -112,11 +159,13 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer three times (the reference kernel for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the rasterizer path is single-GPU (multi-GPU sharding by view is "
-              "described in DESIGN.md but not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the rasterizer path is built and timed on a single GPU (sharding "
+              "by view across GPUs is a design note, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -126,6 +175,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n_el = args.copy_calibration * 2**20 // 4
+        src = torch.ones(n_el, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"copy_bytes": n_el * 4, "repeats": 3}), flush=True)
+        return
     t_setup = time.perf_counter()
     scene, cams = make_config(args.config, args.scale)
     targets = make_target(args.config, cams)
@@ -188,15 +246,48 @@ def main():
     rast.profile(False)
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items() if v > 0))
+    if min(stage_ms[st] for st in STEP_STAGES) <= 0.0:
+        raise SystemExit("stage timing needs --profile-steps >= 1")
     k_sh = (scene.sh_degree + 1) ** 2
-    dom = max(stage_ms, key=stage_ms.get)
-    b = algorithmic_bytes(dom, scene.n, k_sh, len(cams), total_px, rec, pairs)
-    achieved = b / (stage_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b,
-                "duration_ms": stage_ms[dom]}
-    total_b = sum(algorithmic_bytes(s, scene.n, k_sh, len(cams), total_px, rec, pairs)
-                  for s in ("preprocess", "binning", "sort", "raster_fwd", "loss", "raster_bwd", "reduce", "pre_bwd"))
+    pg = 11 + 3 * k_sh
+    keys, vals, _ = rast.debug_binning()
+    n_u = int(np.unique(vals).size)  # Gaussians visible in at least one view
+    del keys, vals
+    evals = rast.count_evaluations(out)
+    composited = int(out["n_contrib"].sum().item())
+    work = {st: stage_work(st, scene.n, n_u, pg, len(cams), total_px, rec, pairs, tiles, evals) for st in STEP_STAGES}
+    stages = {}
+    for st in STEP_STAGES:
+        b, ops = work[st]
+        t = stage_ms[st] * 1e-3
+        e = {"ms": stage_ms[st], "bytes": b, "hbm_frac": b / t / (HBM_PEAK_GBS * 1e9) if t else None}
+        if ops:
+            e.update(ops=ops, alu_frac=ops / t / (VALU_PEAK_TOPS * 1e12) if t else None)
+        stages[st] = e
+    dom = max(STEP_STAGES, key=lambda k: stage_ms[k])
+    b_dom, ops_dom = work[dom]
+    t_dom = stage_ms[dom] * 1e-3
+    kernel = STAGE_KERNEL.get(dom, dom) if args.tile_size == 16 else dom
+    workload = config_names()[args.config]
+    traffic = recorded_traffic(kernel, workload) if args.scale == 1.0 else None
+    if ops_dom:
+        achieved = ops_dom / t_dom / 1e12
+        roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                    "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                    "algorithmic_ops": ops_dom, "ops_per_evaluation": BWD_OPS_PER_EVAL if dom == "raster_bwd"
+                    else FWD_OPS_PER_EVAL, "evaluations": evals, "duration_ms": stage_ms[dom],
+                    "algorithmic_bytes": b_dom, "hbm_frac": b_dom / t_dom / (HBM_PEAK_GBS * 1e9)}
+    else:
+        achieved = b_dom / t_dom / 1e9
+        roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": b_dom,
+                    "duration_ms": stage_ms[dom]}
+    total_b = sum(w[0] for w in work.values())
+    # each stage at the slower of its two bounds, over the measured step
+    ideal_s = sum(max(w[0] / (HBM_PEAK_GBS * 1e9), w[1] / (VALU_PEAK_TOPS * 1e12)) for w in work.values())
+    log(f"dominant {kernel}: {roofline['achieved']:.2f} {roofline['unit']} = {roofline['frac']:.1%} of peak; "
+        f"evaluations {evals} ({composited} composited); step HBM fraction {total_b / (ms * 1e-3) / 8e12:.1%}, "
+        f"combined roofline fraction {ideal_s / (ms * 1e-3):.1%}")
 
     per_view = None
     if not args.no_per_view and len(cams) > 1:
@@ -256,8 +347,13 @@ def main():
         "mpix_per_s": total_px * it_s / 1e6,
         "records": rec,
         "pairs": pairs,
-        "stage_ms": stage_ms,
-        "whole_step_hbm_frac": total_b / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "evaluations": evals,
+        "composited": composited,
+        "visible_gaussians": n_u,
+        "stages": stages,
+        "step_hbm_bytes": total_b,
+        "step_hbm_frac": total_b / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "combined_roofline_frac": ideal_s / (ms * 1e-3),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_view": per_view,

@@ -190,6 +190,17 @@ gsr_status gsr_render_backward_adam(gsr_ctx *ctx, const gsr_gaussians *g, const 
 gsr_status gsr_debug_binning(gsr_ctx *ctx, void *workspace, uint64_t *keys, uint32_t *vals,
                              uint32_t *tile_csr, void *stream);
 
+/* Compositing work of the last forward, for roofline accounting: writes to
+ * *evals (DEVICE, one uint64) the number of (pixel, list entry) pairs with
+ * the entry in front of the pixel's stop position fwd->last_pos and the
+ * pixel inside the entry's pixel box (Sec. 3.3 compositing order), summed
+ * over all pixels of all views.  These are the evaluations the backward
+ * performs; the forward performs the same plus the entries between a
+ * pixel's last composited Gaussian and its stop.  Reads the workspace and
+ * fwd->last_pos only; the count is 0 after a capacity overflow.            */
+gsr_status gsr_count_evaluations(gsr_ctx *ctx, void *workspace, const gsr_fwd_out *fwd, uint64_t *evals,
+                                 void *stream);
+
 /* Synchronise `stream`, then report GSR_ERR_CAPACITY if the last forward ran
  * out of record or pair capacity, else GSR_OK.                              */
 gsr_status gsr_check(gsr_ctx *ctx, void *workspace, void *stream);

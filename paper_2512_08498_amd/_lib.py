@@ -69,6 +69,7 @@ _SIGS = {
                                  C.POINTER(Grads), C.POINTER(Moments), C.POINTER(Moments),
                                  C.POINTER(AdamConfig), P, C.POINTER(Grads), P],
     "gsr_debug_binning": [P, P, P, P, P, P],
+    "gsr_count_evaluations": [P, P, C.POINTER(FwdOut), P, P],
     "gsr_check": [P, P, P],
     "gsr_required_capacity": [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P],
     "gsr_set_sort_routing": [P, C.c_uint32, C.c_int32],

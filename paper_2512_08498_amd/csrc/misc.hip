@@ -1,5 +1,5 @@
-// L1 photometric loss with its gradient, and the binning export used by the
-// parity checks.
+// L1 photometric loss with its gradient, the binning export used by the
+// parity checks, and the compositing work counter.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -97,6 +97,67 @@ void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, 
   (void)views;
   if (sz.t_tot == 0) return;
   k_debug_binning<<<sz.t_tot, 256, 0, st>>>(ws, sz, keys, vals, csr);
+}
+
+// Compositing work of the last forward: for every pixel, the entries of its
+// tile's list in front of its stop position (last_pos) whose pixel box
+// contains the pixel.  These are the (pixel, Gaussian) evaluations the
+// backward must perform; the forward performs these plus the few entries
+// between last_pos and its stop.  One workgroup per tile, boxes staged in
+// LDS; a per-workgroup integer sum is added to *evals.
+__global__ __launch_bounds__(256) void k_count_evals(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
+                                                     const uint32_t *__restrict__ last_pos,
+                                                     unsigned long long *__restrict__ evals) {
+  __shared__ float4 s_box[256];
+  __shared__ unsigned long long s_sum[4];
+  if (ws.scalars[kOverflow]) return;
+  const uint32_t tile = blockIdx.x;
+  const int v = view_of_tile(views, sz.n_views, tile);
+  const ViewInfo vi = views[v];
+  const uint32_t lt = tile - vi.tile_base;
+  const int tx = (int)(lt % (uint32_t)vi.tiles_x), ty = (int)(lt / (uint32_t)vi.tiles_x);
+  const uint32_t start = ws.tile_start[tile], n = ws.tile_count[tile];
+  const uint32_t nrec = ws.scalars[kNumRecords];
+  const int ts = sz.ts, npix = ts * ts;
+  constexpr int kMaxPix = 4;  // 32 x 32 tiles over 256 threads
+  float fx[kMaxPix], fy[kMaxPix];
+  uint32_t last[kMaxPix];
+  for (int p = 0; p < kMaxPix; ++p) {
+    const int q = (int)threadIdx.x + p * 256;
+    const int px = tx * ts + q % ts, py = ty * ts + q / ts;
+    fx[p] = (float)px;
+    fy[p] = (float)py;
+    last[p] = 0;
+    if (q < npix && px < vi.w && py < vi.h)
+      last[p] = min(n, last_pos[vi.pix_off + (uint32_t)py * (uint32_t)vi.w + (uint32_t)px]);
+  }
+  unsigned long long cnt = 0;
+  for (uint32_t b0 = 0; b0 < n; b0 += 256) {
+    const uint32_t m = min(256u, n - b0);
+    __syncthreads();
+    if (threadIdx.x < m) {
+      uint32_t rec = ws.tile_recs[start + b0 + threadIdx.x];
+      if (rec >= nrec) rec = 0;
+      s_box[threadIdx.x] = ws.rec_payload[(size_t)rec * 4];
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < m; ++j) {
+      const float4 box = s_box[j];
+      for (int p = 0; p < kMaxPix; ++p)
+        cnt += (b0 + j < last[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w) ? 1 : 0;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+  if (lane_id() == 0) s_sum[wave_id()] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(evals, (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]));
+}
+
+void launch_count_evals(const ViewInfo *views, const Ws &ws, const Sizes &sz, const uint32_t *last_pos,
+                        uint64_t *evals, hipStream_t st) {
+  launch_zero(reinterpret_cast<uint32_t *>(evals), 2, st);
+  if (sz.t_tot == 0) return;
+  k_count_evals<<<sz.t_tot, 256, 0, st>>>(views, ws, sz, last_pos, reinterpret_cast<unsigned long long *>(evals));
 }
 
 }  // namespace gsr

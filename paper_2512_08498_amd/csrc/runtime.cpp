@@ -451,6 +451,18 @@ gsr_status gsr_debug_binning(gsr_ctx *c, void *ws_base, uint64_t *keys, uint32_t
   return GSR_OK;
 }
 
+gsr_status gsr_count_evaluations(gsr_ctx *c, void *ws_base, const gsr_fwd_out *fwd, uint64_t *evals,
+                                 void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (!ws_base || !fwd || !fwd->last_pos || !evals)
+    return fail(c, GSR_ERR_INVALID_ARG, "NULL argument to gsr_count_evaluations");
+  launch_count_evals(c->views_d, make_ws(c, ws_base), c->sz, fwd->last_pos, evals,
+                     static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
 static gsr_status read_scalars(gsr_ctx *c, void *ws_base, void *stream, uint32_t out[kNumScalars]) {
   if (!c) return GSR_ERR_INVALID_ARG;
   if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");

@@ -196,6 +196,15 @@ class Rasterizer:
     def set_sort_routing(self, small_max=256, force_class=-1):
         self._check(self.lib.gsr_set_sort_routing(self.ctx, int(small_max), int(force_class)))
 
+    def count_evaluations(self, out):
+        """(pixel, list entry) evaluations the last forward's backward walks
+        over (pixel inside the entry's box, entry before the pixel's stop)."""
+        ev = torch.zeros(1, dtype=torch.int64, device=self.device)
+        fo = self._fwd_struct(out)
+        self._check(self.lib.gsr_count_evaluations(self.ctx, _vp(self.workspace), C.byref(fo), _vp(ev),
+                                                   self.stream()))
+        return int(ev.item())
+
     def debug_binning(self):
         """(keys uint64, values uint32, tile CSR) of the last forward, as numpy."""
         _, pairs, tiles = self.required_capacity()

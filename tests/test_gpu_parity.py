@@ -108,3 +108,51 @@ def test_backward_posed_two_views_sh3():
     targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
     log("backward mini rig")
     _check_backward(scene, cams, targets)
+
+
+def _oracle_evaluations(scene, cams, oracle):
+    """Bounds (lo, hi) on the backward's evaluation count from the oracle:
+    per pixel, the Gaussians whose pixel box holds it, up to and including
+    its last composited one in depth order.  An ambiguous pixel may stop
+    anywhere, so it adds 0 to lo and all its boxes to hi."""
+    from oracle.render64 import view_setup
+
+    arrays = scene.arrays()
+    lo = hi = 0
+    for v, cam in enumerate(cams):
+        spec, order, _ = view_setup(arrays, scene.sh_degree, cam)
+        i0, i1, j0, j1 = spec["box"]
+        rank = np.full(scene.n, -1, np.int64)
+        rank[order] = np.arange(len(order))
+        last = oracle[v]["last"]
+        last_rank = np.where(last >= 0, rank[np.maximum(last, 0)], -1)
+        amb = oracle[v]["ambiguous"]
+        for k, g in enumerate(order):
+            sl = (slice(int(j0[g]), int(j1[g]) + 1), slice(int(i0[g]), int(i1[g]) + 1))
+            lo += int(((last_rank[sl] >= k) & ~amb[sl]).sum())
+            hi += int(((last_rank[sl] >= k) | amb[sl]).sum())
+    return lo, hi
+
+
+@pytest.mark.parametrize("ts", [16, 8, 32])
+def test_evaluation_count(cfg1, ts):
+    """The work counter behind the compositing roofline equals the oracle's
+    count at every tile size (the count does not depend on the tiling)."""
+    scene, cams, _ = cfg1
+    oracle = render(scene, cams)
+    rast, params, out = render_gpu(scene, cams, ts=ts)
+    got = rast.count_evaluations(out)
+    lo, hi = _oracle_evaluations(scene, cams, oracle)
+    log(f"ts={ts}: evaluations {got}, oracle [{lo}, {hi}]")
+    assert lo <= got <= hi
+    assert got >= int(out["n_contrib"].sum().item())
+
+
+def test_evaluation_count_rig():
+    scene, cams = mini_rig()
+    oracle = render(scene, cams)
+    rast, params, out = render_gpu(scene, cams, ts=16)
+    got = rast.count_evaluations(out)
+    lo, hi = _oracle_evaluations(scene, cams, oracle)
+    log(f"mini rig: evaluations {got}, oracle [{lo}, {hi}]")
+    assert lo <= got <= hi
