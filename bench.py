@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--tile-size", type=int, default=16)
+    ap.add_argument("--tile-size", type=int, default=16, help="8, 16 or 32; 0 = autotune on the workload")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
@@ -192,11 +192,21 @@ def main():
     params = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.arrays().items()}
     target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in targets])).to(dev)
 
-    rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=args.tile_size, device=dev)
+    cap_rec = max(len(cams) * scene.n // 4, 65536)
+    rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=args.tile_size or 16, device=dev,
+                      capacity_records=cap_rec, capacity_pairs=4 * cap_rec)
     out = rast.forward(params)  # re-plans on capacity overflow
     rec, pairs, tiles = rast.required_capacity()
     # headroom for the scene to move during training
     rast._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
+    tuning = None
+    if args.tile_size == 0:
+        t_tune = time.perf_counter()
+        tuning = rast.autotune(params, repeats=3)
+        out = rast.forward(params)
+        rec, pairs, tiles = rast.required_capacity()
+        rast._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
+        log(f"autotuned in {time.perf_counter() - t_tune:.1f} s: {tuning}")
     out = rast.new_fwd_out()
     log(f"records {rec}, pairs {pairs}, tiles {tiles}, workspace {rast.ws_bytes / 2**30:.2f} GiB")
     opt = FusedAdam(rast, params)
@@ -267,7 +277,7 @@ def main():
     dom = max(STEP_STAGES, key=lambda k: stage_ms[k])
     b_dom, ops_dom = work[dom]
     t_dom = stage_ms[dom] * 1e-3
-    kernel = STAGE_KERNEL.get(dom, dom) if args.tile_size == 16 else dom
+    kernel = STAGE_KERNEL.get(dom, dom) if rast.tile_size == 16 else dom
     workload = config_names()[args.config]
     traffic = recorded_traffic(kernel, workload) if args.scale == 1.0 else None
     if ops_dom:
@@ -291,7 +301,10 @@ def main():
 
     per_view = None
     if not args.no_per_view and len(cams) > 1:
-        rs = [Rasterizer([c], scene.n, scene.sh_degree, tile_size=args.tile_size, device=dev) for c in cams]
+        ll = rast.tuning()["long_list"]
+        rs = [Rasterizer([c], scene.n, scene.sh_degree, tile_size=rast.tile_size, long_list=ll, device=dev,
+                         capacity_records=max(scene.n // 4, 65536), capacity_pairs=max(scene.n, 262144))
+              for c in cams]
         outs = []
         for r in rs:
             o = r.forward(params)
@@ -342,7 +355,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": config_names()[args.config], "views": len(cams), "gaussians": scene.n,
-                   "sh_degree": scene.sh_degree, "pixels": total_px, "tile_size": args.tile_size,
+                   "sh_degree": scene.sh_degree, "pixels": total_px, "tile_size": rast.tile_size,
+                   "tuning": rast.tuning() if tuning is None else tuning,
                    "graph": not args.no_graph, "batched": True},
         "mpix_per_s": total_px * it_s / 1e6,
         "records": rec,

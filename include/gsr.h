@@ -81,7 +81,8 @@ typedef struct {
 } gsr_camera;
 
 typedef struct {
-  int32_t tile_size;        /* 8, 16 or 32 (0 = 16)                                     */
+  int32_t tile_size;        /* 8, 16 or 32; 0 = the context's tuning (16 unless set by
+                               gsr_set_tuning or gsr_autotune)                         */
   int64_t capacity_records; /* visible (view, Gaussian) records; 0 = n_views * n (exact) */
   int64_t capacity_pairs;   /* (record, tile) pairs; 0 = 8 * n_views * n                 */
   float bg[3];              /* background colour                                       */
@@ -115,6 +116,7 @@ void gsr_destroy(gsr_ctx *ctx);
  * Outputs: *workspace_bytes, the size of the caller-allocated DEVICE workspace
  * each render call needs; pix_off (HOST, n_views + 1 entries) the per-view
  * pixel offsets.  Synchronises (uploads the per-view tile table).
+ * The plan also fixes the context's current work split (gsr_tuning).
  * Errors: INVALID_ARG for n_views < 1, n < 0, a non-positive image size, a
  * tile size other than 0/8/16/32, or sizes beyond the 32-bit index range;
  * UNSUPPORTED for sh_degree outside 0..3.                                   */
@@ -238,6 +240,52 @@ gsr_status gsr_profile_read(gsr_ctx *ctx, double *ms, int64_t *calls, int32_t re
  * Results are identical for every setting; this exists so that all sort
  * paths can be exercised on small inputs.  Errors: INVALID_ARG.           */
 gsr_status gsr_set_sort_routing(gsr_ctx *ctx, uint32_t small_max, int32_t force_class);
+
+/* Launch configuration of the compositing kernels.  Images do not depend on
+ * it (the pixel boxes are exact, so the tile size only changes which lists
+ * a Gaussian is binned into); gradients change only by the summation order
+ * of the per-record reductions.
+ *  tile_size  8, 16 or 32.
+ *  long_list  16 px tiles: in the backward, tiles whose list has at least
+ *             this many entries are walked by a workgroup of four waves (an
+ *             8 x 8 quadrant each, one pixel per lane); shorter tiles take one
+ *             wave each (four pixels per lane), four tiles per workgroup.
+ *             0 sends every tile to the four-wave walk, 0xFFFFFFFF none.
+ *  step_ms    (gsr_autotune output) measured forward + backward time.     */
+typedef struct {
+  int32_t tile_size;
+  uint32_t long_list;
+  float step_ms;
+} gsr_tuning;
+
+/* Set the tuning (HOST struct) used by the next gsr_plan, or read the
+ * current one.  Defaults: tile size 16, long_list 512.
+ * Errors: INVALID_ARG for a tile size other than 8/16/32.                  */
+gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
+gsr_status gsr_get_tuning(gsr_ctx *ctx, gsr_tuning *t);
+
+/* Autotuner of the batched launch (the keyframe-window batches of Sec. 3.3
+ * mix resolutions, so no one tile size suits all): times forward plus
+ * backward on this batch for tile sizes 8, 16 and 32 and, at 16, for
+ * long_list in {0, 256, 512, 1024, 0xFFFFFFFF}, and keeps the fastest
+ * (median of `repeats` >= 1 timed passes after one warm-up pass).
+ * g: the Gaussians (DEVICE arrays); cams_host: HOST cameras; opt: capacities
+ * and background as for gsr_plan (tile_size ignored; NULL = defaults).  With
+ * cache_path (NULL = none) the choice is looked up first in that text file,
+ * keyed by the device (architecture and compute units) and the batch shape
+ * (n, SH degree, view sizes), and appended to it after a measurement.
+ * On success *best (HOST) holds the choice, the context's tuning is set to
+ * it and the context is left UNPLANNED: call gsr_plan again (tile size 0
+ * takes the tuned one) and size the workspace from it.  Allocates and frees
+ * its own device buffers (a few times the workspace of one plan) and
+ * synchronises `stream`: not for graph capture.  The gradients it computes
+ * are discarded.  No prior gsr_plan is needed.  Errors: INVALID_ARG (also
+ * when the cache file cannot be written, or a cached line is malformed),
+ * CAPACITY if the batch does not fit 32-bit pair indices, HIP for failed
+ * allocations or launches.                                                  */
+gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams_host, int32_t n_views,
+                        const gsr_plan_options *opt, int32_t repeats, const char *cache_path, gsr_tuning *best,
+                        void *stream);
 
 const char *gsr_last_error(const gsr_ctx *ctx);
 

@@ -40,6 +40,10 @@ class PlanOptions(C.Structure):
                 ("bg", C.c_float * 3)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tile_size", C.c_int32), ("long_list", C.c_uint32), ("step_ms", C.c_float)]
+
+
 class FwdOut(C.Structure):
     _fields_ = [("image", P), ("t_final", P), ("last_pos", P), ("n_contrib", P)]
 
@@ -73,6 +77,10 @@ _SIGS = {
     "gsr_check": [P, P, P],
     "gsr_required_capacity": [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P],
     "gsr_set_sort_routing": [P, C.c_uint32, C.c_int32],
+    "gsr_set_tuning": [P, C.POINTER(Tuning)],
+    "gsr_get_tuning": [P, C.POINTER(Tuning)],
+    "gsr_autotune": [P, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32, C.POINTER(PlanOptions), C.c_int32,
+                     C.c_char_p, C.POINTER(Tuning), P],
     "gsr_profile": [P, C.c_int32],
     "gsr_profile_read": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "gsr_last_error": [P],

@@ -28,6 +28,7 @@ SOURCES = [
     "backward.hip",
     "misc.hip",
     "runtime.cpp",
+    "autotune.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

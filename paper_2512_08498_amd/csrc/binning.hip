@@ -91,8 +91,8 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws, Sizes sz, uint32_t l
   hist[t] = base;
   __syncthreads();
   for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) ws.tile_order[atomicAdd(&hist[bucket(i)], 1u)] = i;
-  // tiles with at least long_list entries come first (long_list is a
-  // multiple of the bucket width); the backward splits them over four waves
+  // tiles with at least long_list entries come first (when long_list is a
+  // multiple of the bucket width, 4); the backward splits them over four waves
   uint32_t nl = 0;
   for (uint32_t i = t; i < sz.t_tot; i += blockDim.x) nl += ws.tile_count[i] >= long_list ? 1u : 0u;
   uint32_t tot_long;
@@ -157,7 +157,7 @@ void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStr
   k_tile_prefix<<<sz.n_views, 1024, 0, st>>>(views, ws);
   k_view_scan<<<1, 64, 0, st>>>(ws, sz);
   k_tile_abs<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(views, ws, sz);
-  k_tile_order<<<1, 1024, 0, st>>>(ws, sz, 512u);
+  k_tile_order<<<1, 1024, 0, st>>>(ws, sz, sz.long_list);
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
   k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz);

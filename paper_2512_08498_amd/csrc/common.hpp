@@ -74,6 +74,7 @@ struct Sizes {
   uint32_t cap_rec;
   uint32_t cap_pairs;
   uint32_t n_blocks;        // ceil(n / kPreBlock)
+  uint32_t long_list;       // 16 px tiles: lists this long are walked by four waves in the backward
   float bg[3];
 };
 

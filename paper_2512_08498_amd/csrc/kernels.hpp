@@ -40,6 +40,7 @@ void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float
                uint32_t *ticket, hipStream_t st);
 void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint64_t *keys,
                           uint32_t *vals, uint32_t *csr, hipStream_t st);
+void launch_fill(float *p, uint64_t n, float value, hipStream_t st);
 void launch_count_evals(const ViewInfo *views, const Ws &ws, const Sizes &sz, const uint32_t *last_pos,
                         uint64_t *evals, hipStream_t st);
 

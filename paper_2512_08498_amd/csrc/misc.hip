@@ -153,6 +153,17 @@ __global__ __launch_bounds__(256) void k_count_evals(const ViewInfo *__restrict_
   if (threadIdx.x == 0) atomicAdd(evals, (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]));
 }
 
+__global__ void k_fill(float *__restrict__ p, uint64_t n, float value) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+void launch_fill(float *p, uint64_t n, float value, hipStream_t st) {
+  if (n == 0) return;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 8192);
+  k_fill<<<(unsigned)blocks, 256, 0, st>>>(p, n, value);
+}
+
 void launch_count_evals(const ViewInfo *views, const Ws &ws, const Sizes &sz, const uint32_t *last_pos,
                         uint64_t *evals, hipStream_t st) {
   launch_zero(reinterpret_cast<uint32_t *>(evals), 2, st);

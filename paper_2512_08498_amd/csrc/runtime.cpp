@@ -11,6 +11,7 @@
 
 #include "gsr.h"
 #include "kernels.hpp"
+#include "runtime.hpp"
 
 using namespace gsr;
 
@@ -42,6 +43,9 @@ struct gsr_ctx {
   uint32_t *loss_ticket = nullptr;
   uint32_t sort_small_max = 256;
   int32_t sort_force_class = -1;
+  // tuning applied at the next gsr_plan
+  int32_t tuned_ts = 16;
+  uint32_t long_list = 512;
   // stage timing
   bool prof = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -223,7 +227,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, GSR_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (sh_degree < 0 || sh_degree > 3) return fail(c, GSR_ERR_UNSUPPORTED, "SH degree %d not in 0..3", sh_degree);
   int32_t ts = opt ? opt->tile_size : 0;
-  if (ts == 0) ts = 16;
+  if (ts == 0) ts = c->tuned_ts;
   if (ts != 8 && ts != 16 && ts != 32) return fail(c, GSR_ERR_INVALID_ARG, "tile size %d not in {8, 16, 32}", ts);
   std::vector<ViewInfo> views(n_views);
   uint64_t tiles = 0, diff = 0, pix = 0;
@@ -271,6 +275,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   s.cap_rec = (uint32_t)cap_rec;
   s.cap_pairs = (uint32_t)cap_pairs;
   s.n_blocks = (uint32_t)((n + kPreBlock - 1) / kPreBlock);
+  s.long_list = c->long_list;
   for (int k = 0; k < 3; ++k) s.bg[k] = opt ? opt->bg[k] : 0.0f;
   c->views = views;
   c->sz = s;
@@ -503,6 +508,25 @@ gsr_status gsr_set_sort_routing(gsr_ctx *c, uint32_t small_max, int32_t force_cl
   return GSR_OK;
 }
 
+gsr_status gsr_set_tuning(gsr_ctx *c, const gsr_tuning *t) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!t) return fail(c, GSR_ERR_INVALID_ARG, "tuning is NULL");
+  if (t->tile_size != 8 && t->tile_size != 16 && t->tile_size != 32)
+    return fail(c, GSR_ERR_INVALID_ARG, "tile size %d not in {8, 16, 32}", t->tile_size);
+  c->tuned_ts = t->tile_size;
+  c->long_list = t->long_list;
+  return GSR_OK;
+}
+
+gsr_status gsr_get_tuning(gsr_ctx *c, gsr_tuning *t) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!t) return fail(c, GSR_ERR_INVALID_ARG, "tuning is NULL");
+  t->tile_size = c->tuned_ts;
+  t->long_list = c->long_list;
+  t->step_ms = 0.0f;
+  return GSR_OK;
+}
+
 gsr_status gsr_profile(gsr_ctx *c, int32_t enable) {
   if (!c) return GSR_ERR_INVALID_ARG;
   if (enable && !c->ev0) {
@@ -529,3 +553,9 @@ gsr_status gsr_profile_read(gsr_ctx *c, double *ms, int64_t *calls, int32_t rese
 const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
 
 }  // extern "C"
+
+gsr_status gsr::ctx_error(gsr_ctx *c, gsr_status s, const char *msg) { return fail(c, s, "%s", msg); }
+
+void gsr::ctx_unplan(gsr_ctx *c) {
+  if (c) c->planned = false;
+}

@@ -44,14 +44,15 @@ class Rasterizer:
     """One planned batch of views over n Gaussians of a fixed SH degree."""
 
     def __init__(self, cams: Sequence, n: int, sh_degree: int, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
-                 capacity_records: int = 0, capacity_pairs: int = 0, device="cuda", cams_device=None):
+                 capacity_records: int = 0, capacity_pairs: int = 0, device="cuda", cams_device=None,
+                 long_list: int = 512):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.n = int(n)
         self.sh_degree = int(sh_degree)
-        self.tile_size = int(tile_size)
+        self.tile_size = int(tile_size) or 16
         self.bg = tuple(float(b) for b in bg)
         self.views = len(cams)
         self.sizes = [(int(c.width), int(c.height)) for c in cams]
@@ -62,6 +63,7 @@ class Rasterizer:
         self.ctx = C.c_void_p()
         L.check(None, self.lib.gsr_create(C.byref(self.ctx)))
         self.workspace = None
+        self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(self.tile_size or 16, long_list, 0.0))))
         self._plan(capacity_records, capacity_pairs)
 
     # -- plan / workspace ------------------------------------------------------------------
@@ -77,6 +79,33 @@ class Rasterizer:
         self.total_px = self.pix_off[-1]
         self.workspace = None
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def tuning(self):
+        t = L.Tuning()
+        self._check(self.lib.gsr_get_tuning(self.ctx, C.byref(t)))
+        return {"tile_size": t.tile_size, "long_list": t.long_list}
+
+    def set_tuning(self, tile_size, long_list=512):
+        """Change the launch configuration and re-plan (same capacities)."""
+        self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(int(tile_size), int(long_list), 0.0))))
+        self.tile_size = int(tile_size)
+        self._plan(*self.capacity)
+
+    def autotune(self, params, repeats=3, cache=None):
+        """Time the candidate launch configurations on this batch (see
+        gsr_autotune), adopt the fastest and re-plan; returns the choice."""
+        g = self._gaussians(params)
+        opts = L.PlanOptions(0, int(self.capacity[0]), int(self.capacity[1]), (C.c_float * 3)(*self.bg))
+        best = L.Tuning()
+        path = None if cache is None else str(cache).encode()
+        self.workspace = None  # the plan is dropped; return its workspace for the measurement
+        torch.cuda.empty_cache()
+        status = self.lib.gsr_autotune(self.ctx, C.byref(g), self._cams_host, self.views, C.byref(opts),
+                                       int(repeats), path, C.byref(best), self.stream())
+        self.tile_size = best.tile_size if status == 0 else self.tile_size
+        self._plan(*self.capacity)
+        self._check(status)
+        return {"tile_size": best.tile_size, "long_list": best.long_list, "step_ms": best.step_ms}
 
     def _check(self, status):
         L.check(self.ctx, status)
