@@ -21,9 +21,8 @@ struct ViewInfo {
   int32_t w, h;          // image size
   int32_t tiles_x, tiles_y;
   uint32_t tile_base;    // first global tile id of the view
-  uint32_t diff_base;    // offset of the view's (tiles_x+1)*(tiles_y+1) difference grid
   uint32_t pix_off;      // first pixel of the view in the flat outputs
-  uint32_t pad;
+  uint32_t pad[2];
 };
 
 // Scalars the kernels exchange through device memory.
@@ -42,8 +41,8 @@ enum Scalar : int {
 // Workspace arrays (device pointers into the caller's workspace).
 struct Ws {
   uint32_t *scalars;        // [kNumScalars]              zeroed per forward
-  int32_t *diff;            // [sum_v (tx+1)(ty+1)]       zeroed per forward
-  uint32_t *tile_cursor;    // [T_tot]                    zeroed per forward
+  uint32_t *tile_count;     // [T_tot] list length        zeroed per forward
+  uint32_t *tile_start;     // [T_tot] list start         zeroed per forward
   uint2 *block_sums;        // [n_blocks] (records, pairs) -> exclusive offsets
   uint32_t *rec_start;      // [n + 1] first record of each Gaussian
   float4 *rec_payload;      // [cap_rec][4] raster payload, see RecPayload
@@ -52,10 +51,10 @@ struct Ws {
   uint32_t *rec_pairoff;    // [cap_rec] first pair of the record (record-major)
   uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t *rec_zbits;      // [cap_rec] depth bits
-  uint32_t *tile_count;     // [T_tot] list length
-  uint32_t *tile_start;     // [T_tot] list start (absolute after k_tile_abs)
   uint32_t *tile_order;     // [T_tot] tiles by decreasing list length
-  uint32_t *view_pair_base; // [n_views + 1]
+  uint32_t *tile_tmp;       // [4][T_tot] keys and values of the tile-order sort
+  uint32_t *radix_hist;     // [256][blocks] digit histograms of the counting passes
+  uint32_t *scan_part;      // chunk sums of the device-wide scans
   uint32_t *queues;         // [3][T_tot] tiles for the larger sorts
   uint64_t *pairs;          // [cap_pairs] (zbits << 32 | record), bucketed by tile
   uint64_t *pairs_tmp;      // [cap_pairs] ping-pong buffer of the global sort
@@ -79,6 +78,9 @@ struct Sizes {
 };
 
 constexpr int kPreBlock = 256;     // Gaussians per preprocess workgroup
+// Per-tile depth sorts by list length: up to 256 entries in one wave, up to
+// kMidMax and kBigMax in LDS by 256 and 512 threads, beyond in global memory.
+constexpr uint32_t kMidMax = 2048, kBigMax = 8192;
 constexpr int kLossBlocks = 2048;  // loss reduction partials
 
 // Image-model constants (float32 bit patterns written as hex literals).

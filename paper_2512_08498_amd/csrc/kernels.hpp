@@ -24,9 +24,10 @@ struct AdamArgs {
 void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
                        const Sizes &sz, int sh_degree, hipStream_t st);
-void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st);
-void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max,
-                 int force_q, hipStream_t st);
+void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t small_max, int force_q,
+                    hipStream_t st);
+void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max, hipStream_t st);
+void launch_tile_csr(const Ws &ws, const Sizes &sz, uint32_t *csr, hipStream_t st);
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
                        uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st);
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,

@@ -76,9 +76,10 @@ void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float
   k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, loss, dl, partials, ticket, vec ? 1 : 0);
 }
 
-// One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian.
+// One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian;
+// the CSR offsets are the exclusive scan of the list lengths.
 __global__ __launch_bounds__(256) void k_debug_binning(Ws ws, Sizes sz, uint64_t *__restrict__ keys,
-                                                       uint32_t *__restrict__ vals, uint32_t *__restrict__ csr) {
+                                                       uint32_t *__restrict__ vals) {
   const uint32_t tile = blockIdx.x;
   const uint32_t start = ws.tile_start[tile], n = ws.tile_count[tile];
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -86,17 +87,14 @@ __global__ __launch_bounds__(256) void k_debug_binning(Ws ws, Sizes sz, uint64_t
     keys[start + i] = ((uint64_t)tile << 32) | ws.rec_zbits[rec];
     vals[start + i] = ws.rec_g[rec];
   }
-  if (threadIdx.x == 0) {
-    csr[tile] = start;
-    if (tile == sz.t_tot - 1) csr[sz.t_tot] = start + n;
-  }
 }
 
 void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint64_t *keys, uint32_t *vals,
                           uint32_t *csr, hipStream_t st) {
   (void)views;
   if (sz.t_tot == 0) return;
-  k_debug_binning<<<sz.t_tot, 256, 0, st>>>(ws, sz, keys, vals, csr);
+  k_debug_binning<<<sz.t_tot, 256, 0, st>>>(ws, sz, keys, vals);
+  launch_tile_csr(ws, sz, csr, st);
 }
 
 // Compositing work of the last forward: for every pixel, the entries of its

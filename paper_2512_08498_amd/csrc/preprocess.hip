@@ -1,5 +1,6 @@
 // Preprocess: project every (view, Gaussian) pair, compact the visible ones
-// into records (Gaussian-major), and count the (record, tile) pairs per tile.
+// into records (Gaussian-major) with their tile rectangles and the offset of
+// their (record, tile) pairs.
 //
 // Two passes over the Gaussians with a scan between them (reduce, then
 // scan, then write), so record indices are deterministic and increase with
@@ -80,8 +81,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Ws ws, Sizes sz) {
 }
 
 template <int DEG>
-__global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam *__restrict__ cams,
-                                                         const ViewInfo *__restrict__ views, Ws ws,
+__global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam *__restrict__ cams, Ws ws,
                                                          Sizes sz, int ts_shift) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
@@ -162,7 +162,6 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
       rgb[ch] = fmaxf(s, 0.0f);
       pass |= (s >= 0.0f ? 1u : 0u) << ch;
     }
-    const ViewInfo vi = views[v];
     ws.rec_payload[(size_t)rec * 4 + 0] = make_float4((float)P.i0, (float)P.i1, (float)P.j0, (float)P.j1);
     ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
     ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
@@ -176,14 +175,6 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
     ws.rec_pairoff[rec] = pair;
     ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
     ws.rec_zbits[rec] = P.zbits;
-    // +1/-1 corners of the tile rectangle in the view's difference grid; a 2D
-    // prefix sum of the grid gives every tile's list length.
-    int32_t *D = ws.diff + vi.diff_base;
-    const int stride = vi.tiles_x + 1;
-    atomicAdd(D + ty0 * stride + tx0, 1);
-    atomicAdd(D + ty0 * stride + tx1 + 1, -1);
-    atomicAdd(D + (ty1 + 1) * stride + tx0, -1);
-    atomicAdd(D + (ty1 + 1) * stride + tx1 + 1, 1);
     rec += 1;
     pair += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   }
@@ -191,15 +182,16 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
 
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
                        const Sizes &sz, int sh_degree, hipStream_t st) {
+  (void)views;
   const int ts_shift = sz.ts == 8 ? 3 : (sz.ts == 16 ? 4 : 5);
   if (sz.n_blocks == 0) return;
   k_pre_count<<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift);
   k_scan_blocks<<<1, 1024, 0, st>>>(ws, sz);
   switch (sh_degree) {
-    case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
-    case 1: k_pre_write<1><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
-    case 2: k_pre_write<2><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
-    default: k_pre_write<3><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
+    case 1: k_pre_write<1><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
+    case 2: k_pre_write<2><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
+    default: k_pre_write<3><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
   }
 }
 

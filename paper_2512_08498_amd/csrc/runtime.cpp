@@ -18,9 +18,9 @@ using namespace gsr;
 namespace {
 
 struct Layout {
-  size_t scalars, diff, cursor, zero_end;
+  size_t scalars, tile_count, tile_start, zero_end;
   size_t block_sums, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
-  size_t tile_count, tile_start, tile_order, vbase, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
+  size_t tile_order, tile_tmp, radix_hist, scan_part, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
   size_t total;
 };
 
@@ -97,8 +97,6 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   const Layout &L = c->lay;
   Ws w;
   w.scalars = reinterpret_cast<uint32_t *>(b + L.scalars);
-  w.diff = reinterpret_cast<int32_t *>(b + L.diff);
-  w.tile_cursor = reinterpret_cast<uint32_t *>(b + L.cursor);
   w.block_sums = reinterpret_cast<uint2 *>(b + L.block_sums);
   w.rec_start = reinterpret_cast<uint32_t *>(b + L.rec_start);
   w.rec_payload = reinterpret_cast<float4 *>(b + L.payload);
@@ -110,7 +108,9 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   w.tile_count = reinterpret_cast<uint32_t *>(b + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t *>(b + L.tile_start);
   w.tile_order = reinterpret_cast<uint32_t *>(b + L.tile_order);
-  w.view_pair_base = reinterpret_cast<uint32_t *>(b + L.vbase);
+  w.tile_tmp = reinterpret_cast<uint32_t *>(b + L.tile_tmp);
+  w.radix_hist = reinterpret_cast<uint32_t *>(b + L.radix_hist);
+  w.scan_part = reinterpret_cast<uint32_t *>(b + L.scan_part);
   w.queues = reinterpret_cast<uint32_t *>(b + L.queues);
   w.pairs = reinterpret_cast<uint64_t *>(b + L.pairs);
   w.pairs_tmp = reinterpret_cast<uint64_t *>(b + L.pairs_tmp);
@@ -121,16 +121,20 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   return w;
 }
 
-Layout make_layout(const Sizes &s, uint32_t diff_words, int32_t n_views) {
+Layout make_layout(const Sizes &s) {
   Layout L{};
   size_t o = 0;
   auto put = [&](size_t &field, size_t bytes) {
     field = o;
     o = align_up(o + bytes);
   };
+  // counting passes of the binning: 8192 items per block, 256 digits; the
+  // device-wide scans take 4096 words per chunk
+  const size_t radix_blocks = std::max<size_t>((std::max<size_t>(s.cap_pairs, s.t_tot) + 8191) / 8192, 1);
+  const size_t scan_words = std::max<size_t>(256 * radix_blocks, (size_t)s.t_tot + 1);
   put(L.scalars, kNumScalars * 4);
-  put(L.diff, (size_t)diff_words * 4);
-  put(L.cursor, (size_t)s.t_tot * 4);
+  put(L.tile_count, (size_t)s.t_tot * 4);
+  put(L.tile_start, (size_t)s.t_tot * 4);
   L.zero_end = o;
   put(L.block_sums, (size_t)s.n_blocks * 8);
   put(L.rec_start, (size_t)(s.n + 1) * 4);
@@ -140,10 +144,10 @@ Layout make_layout(const Sizes &s, uint32_t diff_words, int32_t n_views) {
   put(L.rec_pairoff, (size_t)s.cap_rec * 4);
   put(L.rec_rect, (size_t)s.cap_rec * 8);
   put(L.rec_zbits, (size_t)s.cap_rec * 4);
-  put(L.tile_count, (size_t)s.t_tot * 4);
-  put(L.tile_start, (size_t)s.t_tot * 4);
   put(L.tile_order, (size_t)s.t_tot * 4);
-  put(L.vbase, (size_t)(n_views + 1) * 4);
+  put(L.tile_tmp, (size_t)s.t_tot * 16);
+  put(L.radix_hist, 256 * radix_blocks * 4);
+  put(L.scan_part, (scan_words + 4095) / 4096 * 4);
   put(L.queues, (size_t)s.t_tot * 12);
   put(L.pairs, (size_t)s.cap_pairs * 8);
   put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
@@ -230,7 +234,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   if (ts == 0) ts = c->tuned_ts;
   if (ts != 8 && ts != 16 && ts != 32) return fail(c, GSR_ERR_INVALID_ARG, "tile size %d not in {8, 16, 32}", ts);
   std::vector<ViewInfo> views(n_views);
-  uint64_t tiles = 0, diff = 0, pix = 0;
+  uint64_t tiles = 0, pix = 0;
   for (int v = 0; v < n_views; ++v) {
     const int w = cams[v].width, h = cams[v].height;
     if (w <= 0 || h <= 0 || w > 65535 || h > 65535)
@@ -241,16 +245,14 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
     vi.tiles_x = (w + ts - 1) / ts;
     vi.tiles_y = (h + ts - 1) / ts;
     vi.tile_base = (uint32_t)tiles;
-    vi.diff_base = (uint32_t)diff;
     vi.pix_off = (uint32_t)pix;
-    vi.pad = 0;
+    vi.pad[0] = vi.pad[1] = 0;
     pix_off[v] = (int64_t)pix;
     tiles += (uint64_t)vi.tiles_x * vi.tiles_y;
-    diff += (uint64_t)(vi.tiles_x + 1) * (vi.tiles_y + 1);
     pix += (uint64_t)w * h;
   }
   pix_off[n_views] = (int64_t)pix;
-  if (tiles >= (1ull << 31) || diff >= (1ull << 31) || pix * 3 >= (1ull << 32))
+  if (tiles >= (1ull << 31) || pix * 3 >= (1ull << 32))
     return fail(c, GSR_ERR_INVALID_ARG, "batch too large for 32-bit tile/pixel indices");
   uint64_t cap_rec = opt && opt->capacity_records > 0 ? (uint64_t)opt->capacity_records : (uint64_t)n_views * n;
   uint64_t cap_pairs = opt && opt->capacity_pairs > 0 ? (uint64_t)opt->capacity_pairs : 8ull * n_views * n;
@@ -282,7 +284,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   c->n_views = n_views;
   c->n = n;
   c->sh_degree = sh_degree;
-  c->lay = make_layout(s, (uint32_t)diff, n_views);
+  c->lay = make_layout(s);
   *ws_bytes = c->lay.total;
   c->planned = true;
   return GSR_OK;
@@ -305,11 +307,11 @@ gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_came
   }
   {
     StageTimer tm(c, GSR_STAGE_BINNING, s);
-    launch_binning(c->views_d, ws, c->sz, s);
+    launch_binning(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
   }
   {
     StageTimer tm(c, GSR_STAGE_SORT, s);
-    launch_sort(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
+    launch_sort(c->views_d, ws, c->sz, c->sort_small_max, s);
   }
   {
     StageTimer tm(c, GSR_STAGE_RASTER_FWD, s);

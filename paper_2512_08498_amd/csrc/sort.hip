@@ -153,24 +153,15 @@ __device__ void sort_tile_lds(SortLds<NT, IPT> &S, const Ws &ws, uint32_t start,
   for (uint32_t i = t; i < n; i += NT) ws.tile_recs[start + i] = (uint32_t)src[i];
 }
 
-constexpr uint32_t kSmallMax = 256, kMidMax = 2048, kBigMax = 8192;
-
-__global__ __launch_bounds__(64) void k_sort_small(Ws ws, Sizes sz, uint32_t small_max, int force_q) {
+// Lists of at most small_max entries (the others were queued for the larger
+// sorts by the binning).
+__global__ __launch_bounds__(64) void k_sort_small(Ws ws, Sizes sz, uint32_t small_max) {
   __shared__ SortLds<64, 4> S;
   if (ws.scalars[kOverflow]) return;
   const uint32_t tile = blockIdx.x;
   const uint32_t n = ws.tile_count[tile];
   const uint32_t start = ws.tile_start[tile];
-  if (n == 0) return;
-  if (n > small_max) {
-    if (threadIdx.x == 0) {
-      int q = n <= kMidMax ? 0 : (n <= kBigMax ? 1 : 2);
-      if (force_q > q) q = force_q;
-      const uint32_t at = atomicAdd(ws.scalars + kQueueMid + q, 1u);
-      ws.queues[q * sz.t_tot + at] = tile;
-    }
-    return;
-  }
+  if (n == 0 || n > small_max) return;
   if (n == 1) {
     if (threadIdx.x == 0) ws.tile_recs[start] = (uint32_t)ws.pairs[start];
     return;
@@ -298,13 +289,13 @@ __global__ __launch_bounds__(kHugeNT) void k_sort_huge(Ws ws, Sizes sz) {
   }
 }
 
-// lds_small_max < 256 and force_q (debug options) push shorter lists into a
-// larger size class so every path can be exercised on small inputs.
-void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max,
-                 int force_q, hipStream_t st) {
+// lds_small_max < 256 (a debug option, applied by the binning's size
+// classes as well) pushes shorter lists into the larger sorts so every path
+// can be exercised on small inputs.
+void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max, hipStream_t st) {
   (void)views;
   if (sz.t_tot == 0) return;
-  k_sort_small<<<sz.t_tot, 64, 0, st>>>(ws, sz, lds_small_max, force_q);
+  k_sort_small<<<sz.t_tot, 64, 0, st>>>(ws, sz, lds_small_max);
   k_sort_queue<256, 8><<<1024, 256, 0, st>>>(ws, sz, 0);
   k_sort_queue<512, 16><<<512, 512, 0, st>>>(ws, sz, 1);
   k_sort_huge<<<256, kHugeNT, 0, st>>>(ws, sz);

@@ -88,6 +88,22 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   return __int_as_float(x);
 }
 
+// Lanes below this one in the wave.
+__device__ __forceinline__ uint64_t lanemask_lt() { return (uint64_t(1) << lane_id()) - 1u; }
+
+// Atomic increment of *p for every lane with `pred`, issued once per wave:
+// each such lane gets a distinct old value (in lane order within the wave).
+// Must be reached by all lanes of the wave.
+__device__ __forceinline__ uint32_t wave_atomic_inc(uint32_t *p, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0u;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0u;
+  if (lane_id() == leader) base = atomicAdd(p, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  return base + (uint32_t)__popcll(m & lanemask_lt());
+}
+
 // Tile visited by workgroup `bid` of a grid of `grid` workgroups over `total`
 // tiles.  Consecutive workgroups are dispatched round-robin over the 8 XCDs;
 // this mapping gives each XCD one contiguous run of tiles so neighbouring
