@@ -220,9 +220,9 @@ gsr_status gsr_required_capacity(gsr_ctx *ctx, void *workspace, int64_t *records
  * by gsr_stage, and optionally resets them.                               */
 #define GSR_N_STAGES 9
 typedef enum {
-  GSR_STAGE_PREPROCESS = 0, /* projection, record compaction, tile counting  */
-  GSR_STAGE_BINNING = 1,    /* list offsets and key emission                 */
-  GSR_STAGE_SORT = 2,       /* per-tile radix sort                           */
+  GSR_STAGE_PREPROCESS = 0, /* projection, record compaction                 */
+  GSR_STAGE_BINNING = 1,    /* pair emission, tile sort, list bounds, order  */
+  GSR_STAGE_SORT = 2,       /* depth sort of the records (runs before binning) */
   GSR_STAGE_RASTER_FWD = 3, /* forward compositing                           */
   GSR_STAGE_LOSS = 4,       /* L1 loss and its gradient                      */
   GSR_STAGE_RASTER_BWD = 5, /* backward compositing                          */
@@ -232,14 +232,6 @@ typedef enum {
 } gsr_stage;
 gsr_status gsr_profile(gsr_ctx *ctx, int32_t enable);
 gsr_status gsr_profile_read(gsr_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
-
-/* Test hook for the per-tile sort: tile lists longer than small_max
- * (1..256, default 256) leave the 256-entry LDS sort; force_class >= 0 sends
- * every such list to at least size class force_class (0: 2048-entry LDS sort,
- * 1: 8192-entry LDS sort, 2: global-memory radix sort), -1 chooses by length.
- * Results are identical for every setting; this exists so that all sort
- * paths can be exercised on small inputs.  Errors: INVALID_ARG.           */
-gsr_status gsr_set_sort_routing(gsr_ctx *ctx, uint32_t small_max, int32_t force_class);
 
 /* Launch configuration of the compositing kernels.  Images do not depend on
  * it (the pixel boxes are exact, so the tile size only changes which lists

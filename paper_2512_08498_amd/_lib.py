@@ -76,7 +76,6 @@ _SIGS = {
     "gsr_count_evaluations": [P, P, C.POINTER(FwdOut), P, P],
     "gsr_check": [P, P, P],
     "gsr_required_capacity": [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P],
-    "gsr_set_sort_routing": [P, C.c_uint32, C.c_int32],
     "gsr_set_tuning": [P, C.POINTER(Tuning)],
     "gsr_get_tuning": [P, C.POINTER(Tuning)],
     "gsr_autotune": [P, C.POINTER(Gaussians), C.POINTER(Camera), C.c_int32, C.POINTER(PlanOptions), C.c_int32,

@@ -22,7 +22,6 @@ INCLUDE = os.path.join(ROOT, "include")
 SOURCES = [
     "preprocess.hip",
     "binning.hip",
-    "sort.hip",
     "raster_fwd.hip",
     "raster_bwd.hip",
     "backward.hip",

@@ -1,23 +1,25 @@
-// Tile binning without global atomics on contended addresses:
+// Depth sort and tile binning, as stable counting (LSD radix) passes on
+// 8-bit digits -- no global atomics on contended addresses:
 //
-//  1. emission   every (record, tile) pair is written at its record-major
-//                position (the record's pair offset from the preprocess
-//                scan plus its index in the record's tile rectangle): the
-//                global tile id as key, the record as value;
-//  2. tile sort  stable LSD counting passes on 8-bit digits of the tile id:
-//                per-block digit histograms, a device-wide scan, and a
-//                scatter that ranks each block's items by digit with wave
-//                ballots (stable, so a tile's entries stay in record order,
-//                which is Gaussian order within a view); the last pass
-//                writes the (depth bits << 32 | record) entries the per-tile
-//                depth sorts take;
-//  3. bounds     list start and length of every tile from the sorted ids;
-//  4. classify   size class of each tile for the depth sorts and its
-//                longest-first sort key; the longest-first tile order is two
-//                more counting passes over 16-bit keys.
+//  sort      the visible records by their depth bits (four passes; stable,
+//            so equal depths keep record order, which is Gaussian order
+//            within a view);
+//  emission  every (record, tile) pair in depth-sorted record order: the
+//            global tile id as key, the record as value, at the record's
+//            pair offset (a scan of the rectangle areas in that order);
+//  tile sort the pairs by tile id (two or three passes): being stable, it
+//            leaves each tile's list in (depth, record) order, the
+//            compositing order, so no per-tile sort is needed -- together
+//            the passes sort the 64-bit (tile | depth) keys;
+//  bounds    list start and length of every tile from the sorted ids;
+//  classify  the longest-first key of each tile; the longest-first tile
+//            order is two more passes over 16-bit keys.
 //
-// Far-away Gaussians crowd into the few tiles around the vanishing point of
-// a street scene; per-pair atomic slot claims on those tiles serialise, the
+// A pass is a per-block digit histogram, a device-wide scan of the
+// histograms, and a scatter that ranks each block's items by digit with
+// wave ballots and writes them through LDS in digit runs.  Far-away
+// Gaussians crowd into the few tiles around the vanishing point of a street
+// scene; per-pair atomic slot claims on those tiles would serialise, the
 // counting passes do not.
 #include <algorithm>
 
@@ -26,21 +28,33 @@
 
 namespace gsr {
 
-constexpr int kRdxNT = 256;                        // threads per counting-pass block
-constexpr int kRdxRounds = 32;                     // rounds of 256 items per block
-constexpr uint32_t kRdxChunk = kRdxNT * kRdxRounds;  // items per block
+constexpr int kRdxNT = 256;  // threads per counting-pass block
+// items per lane: 8 (2048 per block) for inputs below kRdxBig items, so a
+// pass spreads over enough workgroups, else 32 (8192 per block)
+constexpr uint32_t kRdxBig = 1u << 23;
 constexpr int kScanNT = 256, kScanIPT = 16;
 constexpr uint32_t kScanChunk = kScanNT * kScanIPT;
+
+// Longest-first code of a list length: 16 steps per octave (the exponent
+// and top four mantissa bits of the length as a float), inverted, so the
+// longest lists come first; lengths from 2^16 up share the first code.
+__device__ __forceinline__ uint32_t length_key(uint32_t n) {
+  if (n == 0) return 255u;
+  const uint32_t code = (__float_as_uint((float)n) >> 19) - (127u << 4);  // 0 for n = 1
+  return 255u - min(code, 255u);
+}
 
 __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t cap) {
   return count_dev ? min(*count_dev, cap) : cap;
 }
 
-// 1. Each wave expands 64 consecutive records into their pairs: lane l takes
-// pair b + l of the wave's concatenated tile rectangles and finds its record
-// by a binary search over the wave's prefix sums, so a big footprint is
-// spread over the lanes.  Positions are record-major and contiguous per wave.
+// Emission: each wave expands 64 consecutive records of the depth order
+// into their pairs: lane l takes pair b + l of the wave's concatenated tile
+// rectangles and finds its record by a binary search over the wave's prefix
+// sums, so a big footprint is spread over the lanes.  offs[i] is the first
+// pair of sorted record i; it is also kept per record for the backward.
 __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
+                                              const uint32_t *__restrict__ perm, const uint32_t *__restrict__ offs,
                                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   if (ws.scalars[kOverflow]) return;
   const uint32_t nrec = ws.scalars[kNumRecords];
@@ -48,17 +62,20 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
   const uint32_t wave_stride = gridDim.x * (blockDim.x / kWave) * kWave;
   for (uint32_t wbase = (blockIdx.x * (blockDim.x / kWave) + wave_id()) * kWave; wbase < nrec;
        wbase += wave_stride) {
-    const uint32_t r = wbase + lane;
-    const bool valid = r < nrec;
-    uint32_t tx0 = 0, w = 1, ty0 = 0, cnt = 0, v = 0, off = 0;
-    if (valid) {
-      const uint2 rc = ws.rec_rect[r];
+    const uint32_t i = wbase + lane;
+    uint32_t tx0 = 0, w = 1, ty0 = 0, cnt = 0, off = 0, rec = 0, tbase = 0, tpitch = 0;
+    if (i < nrec) {
+      rec = perm[i];
+      const uint2 rc = ws.rec_rect[rec];
       tx0 = rc.x & 0xFFFFu;
       w = (rc.x >> 16) - tx0 + 1;
       ty0 = rc.y & 0xFFFFu;
       cnt = w * ((rc.y >> 16) - ty0 + 1);
-      v = ws.rec_view[r];
-      off = ws.rec_pairoff[r];
+      const ViewInfo vi = views[ws.rec_view[rec]];
+      tbase = vi.tile_base;
+      tpitch = (uint32_t)vi.tiles_x;
+      off = offs[i];
+      ws.rec_pairoff[rec] = off;
     }
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t excl = incl - cnt;
@@ -72,16 +89,16 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
         if (e <= p) o += s;
       }
       const uint32_t o_tx0 = __shfl(tx0, o, kWave), o_w = __shfl(w, o, kWave);
-      const uint32_t o_ty0 = __shfl(ty0, o, kWave), o_v = __shfl(v, o, kWave);
-      const uint32_t o_off = __shfl(off, o, kWave), o_ex = __shfl(excl, o, kWave);
+      const uint32_t o_ty0 = __shfl(ty0, o, kWave), o_ex = __shfl(excl, o, kWave);
+      const uint32_t o_off = __shfl(off, o, kWave), o_rec = __shfl(rec, o, kWave);
+      const uint32_t o_base = __shfl(tbase, o, kWave), o_pitch = __shfl(tpitch, o, kWave);
       if (p < total) {
         const uint32_t k = p - o_ex;
         const uint32_t tx = o_tx0 + k % o_w, ty = o_ty0 + k / o_w;
-        const ViewInfo vi = views[o_v];
         const uint32_t pos = o_off + k;
         if (pos < sz.cap_pairs) {
-          keys[pos] = vi.tile_base + ty * (uint32_t)vi.tiles_x + tx;
-          vals[pos] = wbase + (uint32_t)o;
+          keys[pos] = o_base + ty * o_pitch + tx;
+          vals[pos] = o_rec;
         } else {
           ws.scalars[kOverflow] = 3u;  // inconsistent pair offsets
         }
@@ -90,34 +107,69 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
   }
 }
 
-// 2a. Digit histogram of one block's chunk, stored digit-major:
-// hist[d * gridDim.x + block].
+// Lanes of the wave whose digit equals this lane's (8 ballots), among `live`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool live) {
+  uint64_t eq = __ballot(live);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    eq &= bit ? m : ~m;
+  }
+  return eq;
+}
+
+// 2a. Digit histogram of one block's chunk (IPL items per lane), stored
+// digit-major: hist[d * gridDim.x + block].  Each wave loads its items
+// first, then counts them 64 at a time with one LDS atomic per distinct
+// digit.
+template <int IPL>
 __global__ __launch_bounds__(kRdxNT) void k_digit_hist(const uint32_t *__restrict__ scalars,
                                                        const uint32_t *__restrict__ keys,
                                                        const uint32_t *__restrict__ count_dev, uint32_t cap,
                                                        int shift, uint32_t *__restrict__ hist) {
+  constexpr uint32_t CHUNK = kRdxNT * IPL;
   __shared__ uint32_t h[256];
   const uint32_t t = threadIdx.x;
   h[t] = 0u;
   __syncthreads();
   if (!scalars[kOverflow]) {
     const uint32_t n = n_items(count_dev, cap);
-    const uint32_t lo = blockIdx.x * kRdxChunk, hi = min(n, lo + kRdxChunk);
-    for (uint32_t i = lo + t; i < hi; i += kRdxNT) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
+    const uint32_t lo = blockIdx.x * CHUNK + (uint32_t)wave_id() * (CHUNK / 4) + (uint32_t)lane_id();
+    uint32_t d[IPL];
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      const uint32_t i = lo + (uint32_t)r * kWave;
+      d[r] = i < n ? (keys[i] >> shift) & 0xFFu : 0u;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      const bool live = lo + (uint32_t)r * kWave < n;
+      const uint64_t eq = match_digit(d[r], live);
+      if (live && (eq & lt) == 0) atomicAdd(&h[d[r]], (uint32_t)__popcll(eq));
+    }
   }
   __syncthreads();
   hist[t * gridDim.x + blockIdx.x] = h[t];
 }
 
 // Device-wide exclusive scan of data[0, len): chunk sums, a single-block
-// scan of the sums, then each chunk scanned with its offset.
+// scan of the sums, then each chunk scanned with its offset.  Global
+// accesses are coalesced; the per-thread runs of 16 words are read from LDS
+// with a skew of one word per 16, so the 64 lanes hit distinct banks.
+__device__ __forceinline__ uint32_t skew(uint32_t j) { return j + (j >> 4); }
+
 __global__ __launch_bounds__(kScanNT) void k_scan_reduce(const uint32_t *__restrict__ data, uint32_t len,
                                                          uint32_t *__restrict__ part) {
   __shared__ uint32_t s[kScanNT / kWave];
-  const uint32_t lo = blockIdx.x * kScanChunk + threadIdx.x * kScanIPT;
+  const uint32_t lo = blockIdx.x * kScanChunk;
   uint32_t acc = 0;
 #pragma unroll
-  for (int i = 0; i < kScanIPT; ++i) acc += lo + i < len ? data[lo + i] : 0u;
+  for (int i = 0; i < kScanIPT; ++i) {
+    const uint32_t j = lo + (uint32_t)i * kScanNT + threadIdx.x;
+    acc += j < len ? data[j] : 0u;
+  }
   uint32_t total;
   block_excl_scan<kScanNT>(acc, s, total);
   if (threadIdx.x == 0) part[blockIdx.x] = total;
@@ -136,90 +188,162 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ part, 
   }
 }
 
-__global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *__restrict__ data, uint32_t len,
-                                                       const uint32_t *__restrict__ part) {
-  __shared__ uint32_t s[kScanNT / kWave];
-  const uint32_t lo = blockIdx.x * kScanChunk + threadIdx.x * kScanIPT;
-  uint32_t x[kScanIPT], acc = 0;
+// Exclusive scan of NT*16 words at data + lo (words past len read as 0 and
+// are not written), plus `carry`; returns the chunk total.
+template <int NT>
+__device__ __forceinline__ uint32_t scan_chunk(uint32_t *__restrict__ data, uint32_t lo, uint32_t len,
+                                               uint32_t carry, uint32_t *lds, uint32_t *red) {
+  constexpr uint32_t C = NT * 16;
+  const uint32_t t = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < kScanIPT; ++i) {
-    x[i] = lo + i < len ? data[lo + i] : 0u;
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t j = (uint32_t)i * NT + t;
+    lds[skew(j)] = lo + j < len ? data[lo + j] : 0u;
+  }
+  __syncthreads();
+  uint32_t x[16], acc = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    x[i] = lds[skew(t * 16 + i)];
     acc += x[i];
   }
   uint32_t total;
-  uint32_t run = part[blockIdx.x] + block_excl_scan<kScanNT>(acc, s, total);
+  uint32_t run = carry + block_excl_scan<NT>(acc, red, total);
 #pragma unroll
-  for (int i = 0; i < kScanIPT; ++i) {
-    if (lo + i < len) data[lo + i] = run;
+  for (int i = 0; i < 16; ++i) {
+    lds[skew(t * 16 + i)] = run;
     run += x[i];
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t j = (uint32_t)i * NT + t;
+    if (lo + j < len) data[lo + j] = lds[skew(j)];
+  }
+  __syncthreads();
+  (void)C;
+  return total;
 }
 
-// 2b. Stable scatter of one block's chunk by digit.  Per round of 256 items
-// (item = lane order), lanes of a wave with equal digits are found with 8
-// ballots; a lane's rank is the number of such lanes below it plus the
-// counts of the same digit in the lower waves and in earlier rounds.
-// FINAL: the output is the (depth bits << 32 | record) entry, and the
-// sorted key.
-template <bool FINAL>
-__global__ __launch_bounds__(kRdxNT) void k_digit_scatter(
-    const uint32_t *__restrict__ scalars, const uint32_t *__restrict__ keys_in,
-    const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
-    uint64_t *__restrict__ pairs_out, const uint32_t *__restrict__ zbits, const uint32_t *__restrict__ count_dev,
-    uint32_t cap, int shift, const uint32_t *__restrict__ hist) {
+// Small scans in one workgroup of 1024 threads, 16K words per step.
+__global__ __launch_bounds__(1024) void k_scan_one(uint32_t *__restrict__ data, uint32_t len) {
+  __shared__ uint32_t lds[1024 * 16 + 1024];
+  __shared__ uint32_t red[1024 / kWave];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < len; base += 1024u * 16u) carry += scan_chunk<1024>(data, base, len, carry, lds, red);
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *__restrict__ data, uint32_t len,
+                                                       const uint32_t *__restrict__ part) {
+  __shared__ uint32_t lds[kScanChunk + kScanChunk / 16];
+  __shared__ uint32_t red[kScanNT / kWave];
+  scan_chunk<kScanNT>(data, blockIdx.x * kScanChunk, len, part[blockIdx.x], lds, red);
+}
+
+// 2b. Stable scatter of one block's chunk by digit.  Wave w owns the w-th
+// quarter of the chunk and loads all of it first (32 items per lane).  It
+// ranks its items by digit round by round (64 items, in order) with ballot
+// matches and its own running digit counts in LDS, so no workgroup barrier
+// is needed per round.  The block then places its items in LDS in local
+// digit order (stable: waves and rounds in item order) and writes each
+// digit's run to its global offset, contiguously.  vals_in = NULL: the
+// values are the item indices.  With area_out, the values are records and
+// their tile-rectangle areas are written beside them.
+template <int IPL>
+struct ScatterLds {
+  uint32_t key[kRdxNT * IPL];
+  uint32_t val[kRdxNT * IPL];
+  uint32_t wcnt[kRdxNT / kWave][256];  // running, then starting, counts per wave and digit
+  uint32_t lstart[256];                // local start of each digit
+  uint32_t gbase[256];                 // global start of each digit for this block
+  uint32_t scan[kRdxNT / kWave];
+};
+
+template <int IPL>
+__global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__restrict__ scalars,
+                                                          const uint32_t *__restrict__ keys_in,
+                                                          const uint32_t *__restrict__ vals_in,
+                                                          uint32_t *__restrict__ keys_out,
+                                                          uint32_t *__restrict__ vals_out,
+                                                          const uint32_t *__restrict__ count_dev, uint32_t cap,
+                                                          int shift, const uint32_t *__restrict__ hist,
+                                                          const uint2 *__restrict__ rect,
+                                                          uint32_t *__restrict__ area_out) {
   constexpr int NW = kRdxNT / kWave;
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[NW][256];
+  constexpr uint32_t CHUNK = kRdxNT * IPL;
+  __shared__ ScatterLds<IPL> S;
   if (scalars[kOverflow]) return;
   const uint32_t t = threadIdx.x;
   const int w = wave_id(), lane = lane_id();
-  base[t] = hist[t * gridDim.x + blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < NW; ++k) wcnt[k][t] = 0u;
-  __syncthreads();
   const uint32_t n = n_items(count_dev, cap);
-  const uint32_t lo = blockIdx.x * kRdxChunk;
-  const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRdxRounds; ++r) {
-    const uint32_t r0 = lo + (uint32_t)r * kRdxNT;
-    if (r0 >= n) break;  // uniform over the block
-    const uint32_t i = r0 + t;
-    const bool valid = i < n;
-    const uint32_t key = valid ? keys_in[i] : 0u;
-    const uint32_t val = valid ? vals_in[i] : 0u;
-    const uint32_t d = (key >> shift) & 0xFFu;
-    uint64_t eq = __ballot(valid);
+  const uint32_t blo = blockIdx.x * CHUNK;
+  if (blo >= n) return;  // uniform: nothing of this block is live
+  const uint32_t m = min(CHUNK, n - blo);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      eq &= bit ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(eq & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(eq);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      if (pos < cap) {
-        if (FINAL) {
-          pairs_out[pos] = ((uint64_t)zbits[val] << 32) | (uint64_t)val;
-          keys_out[pos] = key;
-        } else {
-          keys_out[pos] = key;
-          vals_out[pos] = val;
-        }
-      }
-    }
-    __syncthreads();
-    uint32_t s = 0;
+  for (int k = 0; k < NW; ++k) S.wcnt[k][t] = 0u;
+  S.gbase[t] = hist[t * gridDim.x + blockIdx.x];
+  const uint32_t lo = blo + (uint32_t)w * (CHUNK / NW);
+  uint32_t key[IPL], val[IPL], rk[IPL];
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const uint32_t i = lo + (uint32_t)r * kWave + (uint32_t)lane;
+    key[r] = i < n ? keys_in[i] : 0u;
+    val[r] = i < n ? (vals_in ? vals_in[i] : i) : 0u;
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const uint32_t i = lo + (uint32_t)r * kWave + (uint32_t)lane;
+    const bool live = i < n;
+    const uint32_t d = (key[r] >> shift) & 0xFFu;
+    const uint64_t eq = match_digit(d, live);
+    const uint32_t before = (uint32_t)__popcll(eq & lt);
+    const uint32_t prior = S.wcnt[w][d];
+    rk[r] = prior + before;
+    if (live && before == 0) S.wcnt[w][d] = prior + (uint32_t)__popcll(eq);
+  }
+  __syncthreads();
+  {
+    uint32_t c[NW], tot = 0;
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-      s += wcnt[k][t];
-      wcnt[k][t] = 0u;
+      c[k] = S.wcnt[k][t];
+      tot += c[k];
     }
-    base[t] += s;
-    __syncthreads();
+    uint32_t total;
+    const uint32_t ls = block_excl_scan<kRdxNT>(tot, S.scan, total);
+    S.lstart[t] = ls;
+    uint32_t run = ls;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      S.wcnt[k][t] = run;
+      run += c[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const uint32_t i = lo + (uint32_t)r * kWave + (uint32_t)lane;
+    if (i < n) {
+      const uint32_t p = S.wcnt[w][(key[r] >> shift) & 0xFFu] + rk[r];
+      S.key[p] = key[r];
+      S.val[p] = val[r];
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = t; j < m; j += kRdxNT) {
+    const uint32_t k = S.key[j], v = S.val[j];
+    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t g = S.gbase[d] + (j - S.lstart[d]);
+    if (g < cap) {
+      keys_out[g] = k;
+      vals_out[g] = v;
+      if (area_out) {  // tile-rectangle area of record v
+        const uint2 rc = rect[v];
+        area_out[g] = ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
+      }
+    }
   }
 }
 
@@ -241,13 +365,9 @@ __global__ void k_tile_bounds(Ws ws, Sizes sz, const uint32_t *__restrict__ tile
   }
 }
 
-// 4. Per tile: the list length; the size class of its depth sort (lists
-// longer than small_max go to a queue of the larger sorts, force_q pushes
-// them to at least that class); the longest-first key; and the number of
-// lists of at least long_list entries.  Queue slots are claimed once per
-// wave.
-__global__ __launch_bounds__(256) void k_tile_classify(Ws ws, Sizes sz, uint32_t small_max, int force_q,
-                                                       uint32_t *__restrict__ order_keys,
+// Per tile: the list length, the longest-first key and the number of lists
+// of at least long_list entries (counted once per wave).
+__global__ __launch_bounds__(256) void k_tile_classify(Ws ws, Sizes sz, uint32_t *__restrict__ order_keys,
                                                        uint32_t *__restrict__ order_vals) {
   if (ws.scalars[kOverflow]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,59 +377,59 @@ __global__ __launch_bounds__(256) void k_tile_classify(Ws ws, Sizes sz, uint32_t
     const uint32_t end = ws.tile_count[t];
     n = end ? end - ws.tile_start[t] : 0u;
     ws.tile_count[t] = n;
-    order_keys[t] = 0xFFFFu - min(n, 0xFFFFu);
+    order_keys[t] = length_key(n);
     order_vals[t] = t;
-  }
-  int q = -1;
-  if (valid && n > small_max) {
-    q = n <= kMidMax ? 0 : (n <= kBigMax ? 1 : 2);
-    if (force_q > q) q = force_q;
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const uint32_t at = wave_atomic_inc(ws.scalars + kQueueMid + c, q == c);
-    if (q == c) ws.queues[(uint32_t)c * sz.t_tot + at] = t;
   }
   (void)wave_atomic_inc(ws.scalars + kNumLong, valid && n >= sz.long_list);
 }
 
 namespace {
 
-struct Pass {
-  const uint32_t *keys_in, *vals_in;
-  uint32_t *keys_out, *vals_out;
-};
+constexpr uint32_t kScanOneMax = 1u << 16;  // scans up to this length take one workgroup
 
 // Exclusive scan of len words in place, part holding ceil(len / 4096) words.
 void scan_words(uint32_t *data, uint32_t len, uint32_t *part, hipStream_t st) {
+  if (len == 0) return;
+  if (len <= kScanOneMax) {
+    k_scan_one<<<1, 1024, 0, st>>>(data, len);
+    return;
+  }
   const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
-  if (nb == 0) return;
   k_scan_reduce<<<nb, kScanNT, 0, st>>>(data, len, part);
   k_scan_top<<<1, 1024, 0, st>>>(part, nb);
   k_scan_down<<<nb, kScanNT, 0, st>>>(data, len, part);
 }
 
-// Stable sort of (keys, vals) by the low `bits` bits of the keys, `cap`
-// items of which *count_dev (or all, if NULL) are live.  The last pass
-// writes FINAL output when pairs_out is given, else to out_vals.
-void counting_sort(const Ws &ws, const uint32_t *count_dev, uint32_t cap, int bits, uint32_t *ka, uint32_t *va,
-                   uint32_t *kb, uint32_t *vb, uint32_t *out_keys, uint32_t *out_vals, uint64_t *pairs_out,
-                   hipStream_t st) {
-  const uint32_t nblk = std::max<uint32_t>((cap + kRdxChunk - 1) / kRdxChunk, 1u);
+uint32_t rdx_chunk(uint32_t cap) { return cap >= kRdxBig ? kRdxNT * 32u : kRdxNT * 8u; }
+
+// Stable sort of `cap` items, of which *count_dev (all if NULL) are live, by
+// the low `bits` bits of their keys.  Input (k0, v0; v0 = NULL: values are
+// the indices); pass p writes (kb, vb) for even p and (ka, va) for odd p,
+// the last pass (out_k, out_v), which must not be its own input.  (ka, va)
+// may be the input itself.  With area_out the last pass also writes the
+// tile-rectangle areas of the (record) values.
+void counting_sort(const Ws &ws, const uint32_t *count_dev, uint32_t cap, int bits, const uint32_t *k0,
+                   const uint32_t *v0, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *out_k,
+                   uint32_t *out_v, uint32_t *area_out, hipStream_t st) {
+  const uint32_t chunk = rdx_chunk(cap);
+  const uint32_t nblk = std::max<uint32_t>((cap + chunk - 1) / chunk, 1u);
   const int passes = std::max(1, (bits + 7) / 8);
-  const uint32_t *kin = ka, *vin = va;
+  const uint32_t *kin = k0, *vin = v0;
   for (int p = 0; p < passes; ++p) {
     const bool last = p == passes - 1;
-    uint32_t *kout = last ? out_keys : (kin == ka ? kb : ka);
-    uint32_t *vout = last ? out_vals : (kin == ka ? vb : va);
-    k_digit_hist<<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, 8 * p, ws.radix_hist);
-    scan_words(ws.radix_hist, 256u * nblk, ws.scan_part, st);
-    if (last && pairs_out) {
-      k_digit_scatter<true><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, nullptr, pairs_out, ws.rec_zbits,
-                                                     count_dev, cap, 8 * p, ws.radix_hist);
+    uint32_t *kout = last ? out_k : (p % 2 == 0 ? kb : ka);
+    uint32_t *vout = last ? out_v : (p % 2 == 0 ? vb : va);
+    uint32_t *aout = last ? area_out : nullptr;
+    if (chunk == kRdxNT * 32u) {
+      k_digit_hist<32><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, 8 * p, ws.radix_hist);
+      scan_words(ws.radix_hist, 256u * nblk, ws.scan_part, st);
+      k_digit_scatter<32><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, count_dev, cap, 8 * p,
+                                                   ws.radix_hist, ws.rec_rect, aout);
     } else {
-      k_digit_scatter<false><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, nullptr, nullptr,
-                                                      count_dev, cap, 8 * p, ws.radix_hist);
+      k_digit_hist<8><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, 8 * p, ws.radix_hist);
+      scan_words(ws.radix_hist, 256u * nblk, ws.scan_part, st);
+      k_digit_scatter<8><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, count_dev, cap, 8 * p,
+                                                  ws.radix_hist, ws.rec_rect, aout);
     }
     kin = kout;
     vin = vout;
@@ -320,27 +440,43 @@ int bit_width(uint32_t x) { return x == 0 ? 0 : 32 - __builtin_clz(x); }
 
 }  // namespace
 
-void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t small_max, int force_q,
-                    hipStream_t st) {
+// Records by depth bits (four passes): the last pass reads rec_tmp[2..3]
+// and writes the order to rec_tmp[0..1] (record indices in rec_tmp[1]) and
+// the records' tile-rectangle areas to rec_tmp[4].
+void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st) {
+  if (sz.cap_rec == 0) return;
+  uint32_t *q[5];
+  for (int k = 0; k < 5; ++k) q[k] = ws.rec_tmp + (size_t)k * sz.cap_rec;
+  counting_sort(ws, ws.scalars + kNumRecords, sz.cap_rec, 32, ws.rec_zbits, nullptr, q[0], q[1], q[2], q[3], q[0],
+                q[1], q[4], st);
+}
+
+void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st) {
   if (sz.t_tot == 0) return;
-  // pair buffers: (tile, record) ping-pong in pairs_tmp and in the
-  // backward's partials (unused until the backward runs)
-  uint32_t *ka = reinterpret_cast<uint32_t *>(ws.pairs_tmp), *va = ka + sz.cap_pairs;
+  const uint32_t *perm = ws.rec_tmp + sz.cap_rec;
+  // areas -> pair offsets; entries past the live records are stale, which
+  // affects no offset of a live record (an exclusive scan looks back only)
+  uint32_t *offs = ws.rec_tmp + 4 * (size_t)sz.cap_rec;
+  scan_words(offs, sz.cap_rec, ws.scan_part, st);
+  // (tile, record) ping-pong in pairs_tmp and in the backward's partials
+  // (unused until the backward runs)
+  uint32_t *ka = ws.pairs_tmp, *va = ka + sz.cap_pairs;
   uint32_t *kb = reinterpret_cast<uint32_t *>(ws.partials), *vb = kb + sz.cap_pairs;
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
-  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz, ka, va);
+  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz, perm, offs, ka, va);
   const int bits = std::max(1, bit_width(sz.t_tot - 1));
   const int passes = (bits + 7) / 8;
-  // the final pass leaves the sorted tile ids in the buffer not read by it
+  // the last pass reads (kb, vb) when the pass count is even, else (ka, va)
   uint32_t *sorted_tiles = (passes % 2 == 1) ? kb : ka;
-  counting_sort(ws, ws.scalars + kNumPairs, sz.cap_pairs, bits, ka, va, kb, vb, sorted_tiles, nullptr, ws.pairs, st);
+  counting_sort(ws, ws.scalars + kNumPairs, sz.cap_pairs, bits, ka, va, ka, va, kb, vb, sorted_tiles, ws.tile_recs,
+                nullptr, st);
   const uint32_t bb = std::min<uint32_t>((sz.cap_pairs + 255) / 256, 16384u);
   k_tile_bounds<<<std::max(bb, 1u), 256, 0, st>>>(ws, sz, sorted_tiles);
   uint32_t *ok = ws.tile_tmp, *ov = ok + sz.t_tot, *ok2 = ov + sz.t_tot, *ov2 = ok2 + sz.t_tot;
-  k_tile_classify<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(ws, sz, small_max, force_q, ok, ov);
-  // longest list first: 16-bit keys, two passes (the second reads ok2/ov2)
-  counting_sort(ws, nullptr, sz.t_tot, 16, ok, ov, ok2, ov2, ok, ws.tile_order, nullptr, st);
+  k_tile_classify<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(ws, sz, ok, ov);
+  // longest list first: one pass over the 8-bit length codes
+  counting_sort(ws, nullptr, sz.t_tot, 8, ok, ov, ok, ov, ok2, ov2, ok2, ws.tile_order, nullptr, st);
 }
 
 // Exclusive scan of the list lengths: the CSR offsets of the tile lists

@@ -30,10 +30,6 @@ enum Scalar : int {
   kNumRecords = 0,    // visible (view, Gaussian) records
   kNumPairs = 1,      // (record, tile) pairs
   kOverflow = 2,      // nonzero: capacity exceeded; later stages skip their work
-  kQueueMid = 3,      // tiles queued for the 2048-entry LDS sort
-  kQueueBig = 4,      // tiles queued for the 8192-entry LDS sort
-  kQueueHuge = 5,     // tiles queued for the global-memory radix sort
-  kLossTicket = 6,    // loss reduction: blocks done
   kNumLong = 7,       // 16 px tiles with a long list (a prefix of tile_order)
   kNumScalars = 16
 };
@@ -51,14 +47,13 @@ struct Ws {
   uint32_t *rec_pairoff;    // [cap_rec] first pair of the record (record-major)
   uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t *rec_zbits;      // [cap_rec] depth bits
+  uint32_t *rec_tmp;        // [5][cap_rec] depth sort of the records, pair offsets
   uint32_t *tile_order;     // [T_tot] tiles by decreasing list length
   uint32_t *tile_tmp;       // [4][T_tot] keys and values of the tile-order sort
   uint32_t *radix_hist;     // [256][blocks] digit histograms of the counting passes
   uint32_t *scan_part;      // chunk sums of the device-wide scans
-  uint32_t *queues;         // [3][T_tot] tiles for the larger sorts
-  uint64_t *pairs;          // [cap_pairs] (zbits << 32 | record), bucketed by tile
-  uint64_t *pairs_tmp;      // [cap_pairs] ping-pong buffer of the global sort
-  uint32_t *tile_recs;      // [cap_pairs] sorted record list of every tile
+  uint32_t *pairs_tmp;      // [2][cap_pairs] tile ids and records of the tile sort
+  uint32_t *tile_recs;      // [cap_pairs] record list of every tile, in depth order
   float4 *partials;         // [cap_pairs][3] backward partial gradients per pair
   float4 *g2d;              // [cap_rec][3] per-record reduced gradients
   float *loss_partials;     // [kLossBlocks]
@@ -78,9 +73,6 @@ struct Sizes {
 };
 
 constexpr int kPreBlock = 256;     // Gaussians per preprocess workgroup
-// Per-tile depth sorts by list length: up to 256 entries in one wave, up to
-// kMidMax and kBigMax in LDS by 256 and 512 threads, beyond in global memory.
-constexpr uint32_t kMidMax = 2048, kBigMax = 8192;
 constexpr int kLossBlocks = 2048;  // loss reduction partials
 
 // Image-model constants (float32 bit patterns written as hex literals).

@@ -24,9 +24,8 @@ struct AdamArgs {
 void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
                        const Sizes &sz, int sh_degree, hipStream_t st);
-void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t small_max, int force_q,
-                    hipStream_t st);
-void launch_sort(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint32_t lds_small_max, hipStream_t st);
+void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st);
+void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_tile_csr(const Ws &ws, const Sizes &sz, uint32_t *csr, hipStream_t st);
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
                        uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st);
@@ -38,7 +37,7 @@ void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Si
 void launch_adam(const MutPtrs &grads, const AdamArgs &a, int64_t n, int sh_degree, hipStream_t st);
 void launch_step_inc(int32_t *step, hipStream_t st);
 void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
-               uint32_t *ticket, hipStream_t st);
+               hipStream_t st);
 void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, uint64_t *keys,
                           uint32_t *vals, uint32_t *csr, hipStream_t st);
 void launch_fill(float *p, uint64_t n, float value, hipStream_t st);

@@ -8,14 +8,13 @@
 namespace gsr {
 
 // loss = sum |img - tgt| / n, dL/dimg = sign(img - tgt) / n.  Per-block
-// partial sums in a fixed order; the last block to finish adds the partials
-// in block order, so the value is deterministic.  float4 accesses when all
-// three arrays are 16-byte aligned.
+// partial sums, then one workgroup adds the partials in block order, so the
+// value is deterministic.  (A last-block ticket would need a device-scope
+// release per block, which on a multi-XCD part writes back the L2.)  float4
+// accesses when all three arrays are 16-byte aligned.
 __global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const float *__restrict__ tgt, int64_t n,
-                                            float *__restrict__ loss, float *__restrict__ dl,
-                                            float *__restrict__ partials, uint32_t *__restrict__ ticket, int vec) {
+                                            float *__restrict__ dl, float *__restrict__ partials, int vec) {
   __shared__ float s_red[4];
-  __shared__ bool s_last;
   const float inv_n = (float)(1.0 / (double)n);
   float acc = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -43,37 +42,29 @@ __global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (lane_id() == 0) s_red[wave_id()] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-    __threadfence();
-    s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// Thread t adds blocks t, t + 256, ... in order; then a fixed-shape tree.
+__global__ __launch_bounds__(256) void k_l1_final(const float *__restrict__ partials, uint32_t nb, int64_t n,
+                                                  float *__restrict__ loss) {
+  __shared__ double s_d[4];
+  double s = 0.0;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) s += (double)partials[b];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane_id() == 0) s_d[wave_id()] = s;
   __syncthreads();
-  if (s_last) {
-    // the last block adds the partials: thread t takes blocks t, t+256, ...
-    // in order, then a fixed-shape tree over the threads
-    __threadfence();
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-      s += (double)__hip_atomic_load(partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
-    __shared__ double s_d[4];
-    if (lane_id() == 0) s_d[wave_id()] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      *loss = (float)(((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)n);
-      *ticket = 0u;
-    }
-  }
+  if (threadIdx.x == 0) *loss = (float)(((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)n);
 }
 
 void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
-               uint32_t *ticket, hipStream_t st) {
+               hipStream_t st) {
   const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
                      reinterpret_cast<uintptr_t>(dl)) & 15u) == 0;
   const int64_t work = vec ? (n + 3) / 4 : n;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, kLossBlocks));
-  k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, loss, dl, partials, ticket, vec ? 1 : 0);
+  k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, dl, partials, vec ? 1 : 0);
+  k_l1_final<<<1, 256, 0, st>>>(partials, (uint32_t)blocks, n, loss);
 }
 
 // One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian;

@@ -20,7 +20,7 @@ namespace {
 struct Layout {
   size_t scalars, tile_count, tile_start, zero_end;
   size_t block_sums, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
-  size_t tile_order, tile_tmp, radix_hist, scan_part, queues, pairs, pairs_tmp, tile_recs, partials, g2d;
+  size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d;
   size_t total;
 };
 
@@ -40,9 +40,6 @@ struct gsr_ctx {
   Sizes sz{};
   Layout lay{};
   float *loss_partials = nullptr;
-  uint32_t *loss_ticket = nullptr;
-  uint32_t sort_small_max = 256;
-  int32_t sort_force_class = -1;
   // tuning applied at the next gsr_plan
   int32_t tuned_ts = 16;
   uint32_t long_list = 512;
@@ -108,12 +105,11 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   w.tile_count = reinterpret_cast<uint32_t *>(b + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t *>(b + L.tile_start);
   w.tile_order = reinterpret_cast<uint32_t *>(b + L.tile_order);
+  w.rec_tmp = reinterpret_cast<uint32_t *>(b + L.rec_tmp);
   w.tile_tmp = reinterpret_cast<uint32_t *>(b + L.tile_tmp);
   w.radix_hist = reinterpret_cast<uint32_t *>(b + L.radix_hist);
   w.scan_part = reinterpret_cast<uint32_t *>(b + L.scan_part);
-  w.queues = reinterpret_cast<uint32_t *>(b + L.queues);
-  w.pairs = reinterpret_cast<uint64_t *>(b + L.pairs);
-  w.pairs_tmp = reinterpret_cast<uint64_t *>(b + L.pairs_tmp);
+  w.pairs_tmp = reinterpret_cast<uint32_t *>(b + L.pairs_tmp);
   w.tile_recs = reinterpret_cast<uint32_t *>(b + L.tile_recs);
   w.partials = reinterpret_cast<float4 *>(b + L.partials);
   w.g2d = reinterpret_cast<float4 *>(b + L.g2d);
@@ -128,10 +124,11 @@ Layout make_layout(const Sizes &s) {
     field = o;
     o = align_up(o + bytes);
   };
-  // counting passes of the binning: 8192 items per block, 256 digits; the
-  // device-wide scans take 4096 words per chunk
-  const size_t radix_blocks = std::max<size_t>((std::max<size_t>(s.cap_pairs, s.t_tot) + 8191) / 8192, 1);
-  const size_t scan_words = std::max<size_t>(256 * radix_blocks, (size_t)s.t_tot + 1);
+  // counting passes of the binning: at least 2048 items per block, 256
+  // digits; the device-wide scans take 4096 words per chunk
+  const size_t items = std::max<size_t>(std::max<size_t>(s.cap_pairs, s.cap_rec), s.t_tot);
+  const size_t radix_blocks = std::max<size_t>((items + 2047) / 2048, 1);
+  const size_t scan_words = std::max<size_t>(std::max<size_t>(256 * radix_blocks, s.cap_rec), (size_t)s.t_tot + 1);
   put(L.scalars, kNumScalars * 4);
   put(L.tile_count, (size_t)s.t_tot * 4);
   put(L.tile_start, (size_t)s.t_tot * 4);
@@ -144,12 +141,11 @@ Layout make_layout(const Sizes &s) {
   put(L.rec_pairoff, (size_t)s.cap_rec * 4);
   put(L.rec_rect, (size_t)s.cap_rec * 8);
   put(L.rec_zbits, (size_t)s.cap_rec * 4);
+  put(L.rec_tmp, (size_t)s.cap_rec * 20);
   put(L.tile_order, (size_t)s.t_tot * 4);
   put(L.tile_tmp, (size_t)s.t_tot * 16);
   put(L.radix_hist, 256 * radix_blocks * 4);
   put(L.scan_part, (scan_words + 4095) / 4096 * 4);
-  put(L.queues, (size_t)s.t_tot * 12);
-  put(L.pairs, (size_t)s.cap_pairs * 8);
   put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
   put(L.tile_recs, (size_t)s.cap_pairs * 4);
   put(L.partials, (size_t)s.cap_pairs * 48);
@@ -203,8 +199,7 @@ gsr_status gsr_create(gsr_ctx **out) {
   if (!out) return GSR_ERR_INVALID_ARG;
   *out = nullptr;
   gsr_ctx *c = new gsr_ctx();
-  if (hipMalloc(&c->loss_partials, kLossBlocks * sizeof(float)) != hipSuccess ||
-      hipMalloc(&c->loss_ticket, 256) != hipSuccess || hipMemset(c->loss_ticket, 0, 256) != hipSuccess) {
+  if (hipMalloc(&c->loss_partials, kLossBlocks * sizeof(float)) != hipSuccess) {
     gsr_destroy(c);
     return GSR_ERR_HIP;
   }
@@ -218,7 +213,6 @@ void gsr_destroy(gsr_ctx *c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->loss_partials) (void)hipFree(c->loss_partials);
-  if (c->loss_ticket) (void)hipFree(c->loss_ticket);
   delete c;
 }
 
@@ -306,12 +300,12 @@ gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_came
     launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, s);
   }
   {
-    StageTimer tm(c, GSR_STAGE_BINNING, s);
-    launch_binning(c->views_d, ws, c->sz, c->sort_small_max, c->sort_force_class, s);
+    StageTimer tm(c, GSR_STAGE_SORT, s);
+    launch_depth_sort(ws, c->sz, s);
   }
   {
-    StageTimer tm(c, GSR_STAGE_SORT, s);
-    launch_sort(c->views_d, ws, c->sz, c->sort_small_max, s);
+    StageTimer tm(c, GSR_STAGE_BINNING, s);
+    launch_binning(c->views_d, ws, c->sz, s);
   }
   {
     StageTimer tm(c, GSR_STAGE_RASTER_FWD, s);
@@ -328,8 +322,7 @@ gsr_status gsr_l1_loss(gsr_ctx *c, const float *image, const float *target, int6
   if (n_elems <= 0) return fail(c, GSR_ERR_INVALID_ARG, "n_elems must be positive");
   {
     StageTimer tm(c, GSR_STAGE_LOSS, static_cast<hipStream_t>(stream));
-    launch_l1(image, target, n_elems, loss_out, dL_dimage, c->loss_partials, c->loss_ticket,
-              static_cast<hipStream_t>(stream));
+    launch_l1(image, target, n_elems, loss_out, dL_dimage, c->loss_partials, static_cast<hipStream_t>(stream));
   }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
@@ -498,15 +491,6 @@ gsr_status gsr_required_capacity(gsr_ctx *c, void *ws_base, int64_t *records, in
   if (records) *records = sc[kNumRecords];
   if (pairs) *pairs = sc[kNumPairs];
   if (tiles) *tiles = c->sz.t_tot;
-  return GSR_OK;
-}
-
-gsr_status gsr_set_sort_routing(gsr_ctx *c, uint32_t small_max, int32_t force_class) {
-  if (!c) return GSR_ERR_INVALID_ARG;
-  if (small_max < 1 || small_max > 256 || force_class < -1 || force_class > 2)
-    return fail(c, GSR_ERR_INVALID_ARG, "small_max must be in 1..256 and force_class in -1..2");
-  c->sort_small_max = small_max;
-  c->sort_force_class = force_class;
   return GSR_OK;
 }
 

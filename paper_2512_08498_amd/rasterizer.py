@@ -222,9 +222,6 @@ class Rasterizer:
         self._check(self.lib.gsr_profile_read(self.ctx, ms, calls, 1 if reset else 0))
         return {name: (ms[i], calls[i]) for i, name in enumerate(L.STAGE_NAMES)}
 
-    def set_sort_routing(self, small_max=256, force_class=-1):
-        self._check(self.lib.gsr_set_sort_routing(self.ctx, int(small_max), int(force_class)))
-
     def count_evaluations(self, out):
         """(pixel, list entry) evaluations the last forward's backward walks
         over (pixel inside the entry's box, entry before the pixel's stop)."""

@@ -17,10 +17,8 @@ def device_params(scene, device="cuda"):
     return {k: torch.from_numpy(np.ascontiguousarray(v)).to(device) for k, v in scene.arrays().items()}
 
 
-def render_gpu(scene, cams, ts=16, bg=(0.0, 0.0, 0.0), routing=None, **kw):
+def render_gpu(scene, cams, ts=16, bg=(0.0, 0.0, 0.0), **kw):
     rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=ts, bg=bg, **kw)
-    if routing is not None:
-        rast.set_sort_routing(*routing)
     params = device_params(scene)
     out = rast.forward(params)
     torch.cuda.synchronize()

@@ -167,15 +167,24 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("routing", [(1, 0), (1, 1), (1, 2), (64, 2)])
-def test_every_sort_path_is_bit_exact(routing):
-    scene_, cams = make_config(3, scale=0.01)
-    log(f"sort routing {routing}")
-    rast, params, out = render_gpu(scene_, cams, routing=routing)
+@pytest.mark.parametrize("case", ["one_pass", "two_passes", "three_passes"])
+def test_tile_sort_pass_counts_bit_exact(case):
+    """The tile sort takes one, two or three 8-bit counting passes by the
+    number of tiles in the batch (12, 34,200 and 271,200 tiles here)."""
+    if case == "one_pass":
+        scene_, cams = make_config(1)
+        ts = 16
+    else:
+        scene_, cams = make_config(3, scale=0.01)
+        ts = 16 if case == "two_passes" else 8
+        if case == "three_passes":
+            cams = cams + cams
+    rast, params, out = render_gpu(scene_, cams, ts=ts)
+    log(f"{case}: {rast.required_capacity()[2]} tiles")
     keys, vals, csr = rast.debug_binning()
-    okeys, ovals, ocsr = tile_lists(scene_, cams, 16)
+    okeys, ovals, ocsr = tile_lists(scene_, cams, ts)
     assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals) and np.array_equal(csr, ocsr)
-    ref, _, ref_out = render_gpu(scene_, cams)
+    ref, _, ref_out = render_gpu(scene_, cams, ts=32)
     assert torch.equal(out["image"], ref_out["image"])
 
 
@@ -187,10 +196,10 @@ def test_sort_orders_equal_depths_by_gaussian_index():
     sc = scene(means, np.full((n, 3), -2.0), [[1, 0, 0, 0]] * n, rng.normal(0, 1, n),
                colours=rng.uniform(0, 1, (n, 3)))
     cams = [camera(60.0)]
-    for routing in (None, (1, 0), (1, 2)):
-        rast, params, out = render_gpu(sc, cams, routing=routing)
+    for ts in (8, 16, 32):
+        rast, params, out = render_gpu(sc, cams, ts=ts)
         keys, vals, csr = rast.debug_binning()
-        okeys, ovals, ocsr = tile_lists(sc, cams, 16)
+        okeys, ovals, ocsr = tile_lists(sc, cams, ts)
         assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals)
 
 
@@ -240,7 +249,7 @@ def test_abi_rejects_invalid_arguments(cfg1):
     st = lib.gsr_render_forward(rast2.ctx, C.byref(g), C.c_void_p(rast2.cams_dev.data_ptr()), 1,
                                 C.c_void_p(rast2.workspace.data_ptr()), rast2.ws_bytes, C.byref(fo), rast2.stream())
     assert st == L.GSR_ERR_NOT_PLANNED
-    assert lib.gsr_set_sort_routing(rast2.ctx, 0, -1) == L.GSR_ERR_INVALID_ARG
+    assert lib.gsr_set_tuning(rast2.ctx, C.byref(L.Tuning(12, 512, 0.0))) == L.GSR_ERR_INVALID_ARG
 
 
 def _edge_check(sc, cams, ts=16):

@@ -24,8 +24,8 @@ IMG_TOL = 1e-5
 GRAD_TOL = 1e-4
 
 
-def _check_forward(scene, cams, ts, oracle=None, routing=None):
-    rast, params, out = render_gpu(scene, cams, ts=ts, routing=routing)
+def _check_forward(scene, cams, ts, oracle=None):
+    rast, params, out = render_gpu(scene, cams, ts=ts)
     keys, vals, csr = rast.debug_binning()
     okeys, ovals, ocsr = tile_lists(scene, cams, ts)
     assert len(keys) == len(okeys)
