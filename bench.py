@@ -58,10 +58,10 @@ def stage_work(stage, n, n_u, pg, views, px, rec, pairs, tiles, evals):
     read and written once), and the compositing evaluations."""
     if stage == "preprocess":   # params in (visible ones whole), records out; visibility scan
         return 12 * n + 4 * (pg - 3) * n_u + 4 * views * n + 48 * rec + 8 * views * n, 0
-    if stage == "binning":      # records in; (key, value) pairs out
-        return 24 * rec + 12 * pairs, 0
-    if stage == "sort":         # pairs in and out; tile ranges
-        return 24 * pairs + 8 * pairs + 8 * tiles, 0
+    if stage == "binning":      # records in, (key, value) pairs out; tile ranges
+        return 24 * rec + 12 * pairs + 8 * pairs + 8 * tiles, 0
+    if stage == "sort":         # (key, value) pairs in and out
+        return 24 * pairs, 0
     if stage == "raster_fwd":   # lists + records in; image, T, last, count out
         return 40 * pairs + 20 * px, FWD_OPS_PER_EVAL * evals
     if stage == "loss":         # image + target in; gradient out
