@@ -180,10 +180,16 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
         in[p] = pos < last[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w;
         any_in |= in[p];
       }
-      // q-gradients are accumulated without the ln 2 of d alpha / dq,
-      // applied once to the wave sums below
+      // (wave-uniform) records no pixel of the wave touches cost only the tests
+      if (__ballot(any_in) == 0) continue;
+      // q-gradients are accumulated without the ln 2 of d alpha / dq, applied
+      // once to the sums in the epilogue.  The empty asm keeps the zeros
+      // opaque, so the compiler does not re-materialise them on every path
+      // through the per-pixel branches.
       float a_offx = 0.f, a_offy = 0.f, a_qa = 0.f, a_qb = 0.f, a_qc = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f,
             a_b = 0.f;
+      asm volatile("" : "+v"(a_offx), "+v"(a_offy), "+v"(a_qa), "+v"(a_qb), "+v"(a_qc), "+v"(a_o), "+v"(a_r),
+                   "+v"(a_g), "+v"(a_b));
       bool any = false;
       if (any_in) {
         const float4 q1 = L.p1[jj], q2 = L.p2[jj];
@@ -228,15 +234,15 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
         }
       }
       if (__ballot(any)) {
-        const float r0 = wave_sum_to_lane63(a_offx), r1 = wave_sum_to_lane63(a_offy);
-        const float r2 = wave_sum_to_lane63(a_qa), r3 = wave_sum_to_lane63(a_qb);
-        const float r4 = wave_sum_to_lane63(a_qc), r5 = wave_sum_to_lane63(a_o);
-        const float r6 = wave_sum_to_lane63(a_r), r7 = wave_sum_to_lane63(a_g);
-        const float r8 = wave_sum_to_lane63(a_b);
-        if (lane == kWave - 1) {
+        const float v9[9] = {a_offx, a_offy, a_qa, a_qb, a_qc, a_o, a_r, a_g, a_b};
+        float t3[3];
+        wave_sum9(v9, t3);
+        if ((lane & 15) == 0) {
+          const int k = lane >> 4, i = 2 * (k & 1) + (k >> 1);
           float *dst = L.g + ((size_t)jj * NW + wv) * 9;
-          dst[0] = r0 * kLn2; dst[1] = r1 * kLn2; dst[2] = r2 * kLn2; dst[3] = r3 * kLn2;
-          dst[4] = r4 * kLn2; dst[5] = r5; dst[6] = r6; dst[7] = r7; dst[8] = r8;
+          dst[i] = t3[0];
+          dst[4 + i] = t3[1];
+          if (k == 0) dst[8] = t3[2];
         }
       }
     }
@@ -250,8 +256,8 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
 #pragma unroll
         for (int c = 0; c < 9; ++c) s9[c] += L.g[((size_t)e * NW + w) * 9 + c];
       const uint32_t slot = L.out[e];
-      ws.partials[(size_t)slot * 3 + 0] = make_float4(s9[0], s9[1], s9[2], s9[3]);
-      ws.partials[(size_t)slot * 3 + 1] = make_float4(s9[4], s9[5], s9[6], s9[7]);
+      ws.partials[(size_t)slot * 3 + 0] = make_float4(s9[0] * kLn2, s9[1] * kLn2, s9[2] * kLn2, s9[3] * kLn2);
+      ws.partials[(size_t)slot * 3 + 1] = make_float4(s9[4] * kLn2, s9[5], s9[6], s9[7]);
       ws.partials[(size_t)slot * 3 + 2] = make_float4(s9[8], 0.0f, 0.0f, 0.0f);
     }
     hi = lo;

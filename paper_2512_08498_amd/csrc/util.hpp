@@ -68,6 +68,70 @@ __device__ __forceinline__ T wave_reduce_max(T x) {
 
 // Sum over the wave with DPP row operations; the total is valid in lane 63.
 // Must be called with all 64 lanes active.
+// Sum over each row of 16 lanes, in every lane of the row (four DPP steps).
+__device__ __forceinline__ float row_sum16(float v) {
+  int x = __float_as_int(v);
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
+  return __int_as_float(x);
+}
+
+// Swap-and-add of two row-summed values a, b: lanes 0..31 get
+// a[l] + a[l + 32], lanes 32..63 get b[l - 32] + b[l].
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
+}
+
+// Swap-and-add of two fold32 results x (values A | B) and y (C | D): lanes
+// 0..15 get A, 16..31 get C, 32..47 get B, 48..63 get D, each summed over
+// the whole wave.
+__device__ __forceinline__ float fold16(float x, float y) {
+  const auto h = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
+}
+
+// Wave sums of nine values in a fixed order (deterministic).  On return,
+// lane 16k (k = 0..3) holds the sum of v[i(k)] in t[0] and of v[4 + i(k)]
+// in t[1], with i(k) = 2 (k & 1) + (k >> 1); lanes 0..15 hold the sum of v[8]
+// in t[2].  Every lane of the wave must be active.
+__device__ __forceinline__ void wave_sum9(const float (&v)[9], float (&t)[3]) {
+  float r[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) r[c] = row_sum16(v[c]);
+  const float s01 = fold32(r[0], r[1]), s23 = fold32(r[2], r[3]);
+  const float s45 = fold32(r[4], r[5]), s67 = fold32(r[6], r[7]);
+  const float s88 = fold32(r[8], r[8]);
+  t[0] = fold16(s01, s23);
+  t[1] = fold16(s45, s67);
+  t[2] = fold16(s88, s88);
+}
+
+// Sum over the 64 lanes, in every lane: the row sums by four DPP steps,
+// then rows (0+2, 1+3) by a 32-lane swap and (0+1, 2+3) by a 16-lane swap.
+// Fixed order, so the result is deterministic; every lane must be active.
+__device__ __forceinline__ float wave_sum_all(float v) {
+  int x = __float_as_int(v);
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
+  x = __float_as_int(__int_as_float(x) +
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  const float s2 = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(s2), __float_as_uint(s2), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   int x = __float_as_int(v);
   // quad butterflies: lanes (0,1,2,3) -> (1,0,3,2) then (2,3,0,1)
