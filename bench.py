@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--tile-size", type=int, default=16, help="8, 16 or 32; 0 = autotune on the workload")
+    ap.add_argument("--tile-size", type=int, default=0, help="8, 16 or 32; 0 (default) = autotune on the workload")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")

@@ -251,7 +251,7 @@ typedef struct {
 } gsr_tuning;
 
 /* Set the tuning (HOST struct) used by the next gsr_plan, or read the
- * current one.  Defaults: tile size 16, long_list 512.
+ * current one.  Defaults: tile size 16, long_list 1024.
  * Errors: INVALID_ARG for a tile size other than 8/16/32.                  */
 gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
 gsr_status gsr_get_tuning(gsr_ctx *ctx, gsr_tuning *t);

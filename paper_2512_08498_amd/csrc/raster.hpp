@@ -23,10 +23,11 @@
 
 namespace gsr {
 
-// Forward: all waves of the workgroup share the tile's LDS batch, each wave
-// an 8 x 8 block with one pixel per lane (four pixels per lane, one per
-// 16 x 16 quadrant, at TS = 32).  Sharing a tile over four waves shortens the
-// critical path of long lists.
+// Forward at 8 and 32 px (and for long lists at 16 px): all waves of the
+// workgroup share the tile's LDS batch, each wave an 8 x 8 block with one
+// pixel per lane (four pixels per lane, one per 16 x 16 quadrant, at
+// TS = 32).  Sharing a tile over four waves shortens the critical path of
+// long lists.
 template <int TS>
 struct FwdTile {
   static constexpr int NT = TS == 8 ? 64 : 256;

@@ -177,7 +177,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       bool any_in = false;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        in[p] = pos < last[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w;
+        in[p] = (pos < last[p]) & (fx[p] >= box.x) & (fx[p] <= box.y) & (fy[p] >= box.z) & (fy[p] <= box.w);
         any_in |= in[p];
       }
       // (wave-uniform) records no pixel of the wave touches cost only the tests

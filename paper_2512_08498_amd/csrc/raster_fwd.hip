@@ -2,28 +2,49 @@
 // list, with per-pixel early termination once transmittance would fall
 // below 1e-4 and a workgroup-level exit once every pixel has stopped.
 //
-// Records are staged in LDS in batches of NT (one per thread, four float4
-// each, stored as four arrays so all lanes read the same address: LDS
-// broadcast).  Per pixel the kernel keeps T, the colour and the position one
-// past the last composited entry, which the backward pass starts from.
+// Records are staged in LDS in batches (one per thread, four float4 each,
+// stored as four arrays so all lanes read the same address: LDS broadcast).
+// Per pixel the kernel keeps T, the colour and the position one past the
+// last composited entry, which the backward pass starts from.
 #include "kernels.hpp"
 #include "raster.hpp"
 #include "util.hpp"
 
 namespace gsr {
 
-template <int TS>
-__global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *__restrict__ views, Ws ws,
-                                                                Sizes sz, float *__restrict__ image,
-                                                                float *__restrict__ t_final,
-                                                                uint32_t *__restrict__ last_pos,
-                                                                uint32_t *__restrict__ n_contrib) {
-  constexpr int NT = FwdTile<TS>::NT, PPT = FwdTile<TS>::PPT, B = NT;
-  __shared__ float4 s_p0[B], s_p1[B], s_p2[B], s_p3[B];
-  if (ws.scalars[kOverflow]) return;
-  if (blockIdx.x >= sz.t_tot) return;
-  const uint32_t tile = ws.tile_order[blockIdx.x];
-  const int t = threadIdx.x;
+// Barrier over the threads that share one tile's LDS: the workgroup, or a
+// single wave (whose LDS accesses are performed in order).
+template <bool WG>
+__device__ __forceinline__ void fwd_sync() {
+  if (WG) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <bool WG>
+__device__ __forceinline__ bool group_any(bool x) {
+  if (WG) return __syncthreads_or(x ? 1 : 0) != 0;
+  fwd_sync<false>();
+  return __ballot(x) != 0;
+}
+
+template <int B>
+struct FwdLds {
+  float4 p0[B], p1[B], p2[B], p3[B];
+};
+
+// Front-to-back walk over one tile's list by a group of NT threads (a
+// workgroup when WG, else one wave), each thread holding PPT pixels given by
+// `pix(t, p, x, y)` relative to the tile origin; records are staged in LDS
+// in batches of B.
+template <int TS, int NT, int PPT, bool WG, int B, class Pix>
+__device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, const Ws &ws, const Sizes &sz,
+                                         uint32_t tile, int t, FwdLds<B> &L, float *__restrict__ image,
+                                         float *__restrict__ t_final, uint32_t *__restrict__ last_pos,
+                                         uint32_t *__restrict__ n_contrib, Pix pix) {
   const int v = view_of_tile(views, sz.n_views, tile);
   const ViewInfo vi = views[v];
   const uint32_t lt = tile - vi.tile_base;
@@ -38,7 +59,7 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     int x, y;
-    fwd_pixel<TS>(t, p, x, y);
+    pix(t, p, x, y);
     px[p] = tx * TS + x;
     py[p] = ty * TS + y;
     fx[p] = (float)px[p];
@@ -51,10 +72,10 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
   }
 
   for (uint32_t b0 = 0; b0 < n; b0 += B) {
-    int alive = 0;
+    bool alive = false;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) alive |= done[p] ? 0 : 1;
-    if (!__syncthreads_or(alive)) break;
+    for (int p = 0; p < PPT; ++p) alive |= !done[p];
+    if (!group_any<WG>(alive)) break;
     const uint32_t m = min((uint32_t)B, n - b0);
     if ((uint32_t)t < m) {
       uint32_t rec = ws.tile_recs[start + b0 + t];
@@ -63,19 +84,20 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
         rec = 0;
       }
       const float4 *src = ws.rec_payload + (size_t)rec * 4;
-      s_p0[t] = src[0];
-      s_p1[t] = src[1];
-      s_p2[t] = src[2];
-      s_p3[t] = src[3];
+      L.p0[t] = src[0];
+      L.p1[t] = src[1];
+      L.p2[t] = src[2];
+      L.p3[t] = src[3];
     }
-    __syncthreads();
+    fwd_sync<WG>();
     for (uint32_t j = 0; j < m; ++j) {
-      const float4 box = s_p0[j];
+      const float4 box = L.p0[j];
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        const bool in = !done[p] && fx[p] >= box.x && fx[p] <= box.y && fy[p] >= box.z && fy[p] <= box.w;
+        // bitwise, so the whole box is tested at once with a single branch
+        const bool in = !done[p] & (fx[p] >= box.x) & (fx[p] <= box.y) & (fy[p] >= box.z) & (fy[p] <= box.w);
         if (in) {
-          const float4 q1 = s_p1[j], q2 = s_p2[j];
+          const float4 q1 = L.p1[j], q2 = L.p2[j];
           const float dx = (fx[p] - box.x) - q1.x;
           const float dy = (fy[p] - box.z) - q1.y;
           const float u = fmaf(q1.w, dy, dx);
@@ -87,7 +109,7 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
               done[p] = true;
             } else {
               const float w = alpha * T[p];
-              const float b = s_p3[j].x;
+              const float b = L.p3[j].x;
               C0[p] = fmaf(w, q2.z, C0[p]);
               C1[p] = fmaf(w, q2.w, C1[p]);
               C2[p] = fmaf(w, b, C2[p]);
@@ -105,16 +127,68 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
   for (int p = 0; p < PPT; ++p) {
     if (px[p] < vi.w && py[p] < vi.h) {
       const uint32_t hw = (uint32_t)vi.w * (uint32_t)vi.h;
-      const uint32_t pix = (uint32_t)py[p] * (uint32_t)vi.w + (uint32_t)px[p];
+      const uint32_t pixi = (uint32_t)py[p] * (uint32_t)vi.w + (uint32_t)px[p];
       float *img = image + (size_t)3 * vi.pix_off;
-      img[pix] = C0[p] + T[p] * sz.bg[0];
-      img[hw + pix] = C1[p] + T[p] * sz.bg[1];
-      img[2 * hw + pix] = C2[p] + T[p] * sz.bg[2];
-      t_final[vi.pix_off + pix] = T[p];
-      last_pos[vi.pix_off + pix] = last[p];
-      n_contrib[vi.pix_off + pix] = cnt[p];
+      img[pixi] = C0[p] + T[p] * sz.bg[0];
+      img[hw + pixi] = C1[p] + T[p] * sz.bg[1];
+      img[2 * hw + pixi] = C2[p] + T[p] * sz.bg[2];
+      t_final[vi.pix_off + pixi] = T[p];
+      last_pos[vi.pix_off + pixi] = last[p];
+      n_contrib[vi.pix_off + pixi] = cnt[p];
     }
   }
+}
+
+// 16 px tiles: lists of at least long_list entries (a prefix of the
+// longest-first order) are shared by four waves, one 8 x 8 quadrant each
+// with one pixel per lane; the other tiles take one wave each (16 x 16
+// pixels, four per lane), four tiles per workgroup, so each record is tested
+// once per tile rather than once per quadrant.
+union FwdLds16 {
+  FwdLds<256> quad;
+  FwdLds<64> wave[4];
+};
+
+__global__ __launch_bounds__(256) void k_raster_fwd16(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
+                                                      float *__restrict__ image, float *__restrict__ t_final,
+                                                      uint32_t *__restrict__ last_pos,
+                                                      uint32_t *__restrict__ n_contrib) {
+  __shared__ FwdLds16 S;
+  if (ws.scalars[kOverflow]) return;
+  const uint32_t n_long = ws.scalars[kNumLong];
+  const int t = threadIdx.x;
+  if (blockIdx.x < n_long) {
+    fwd_walk<16, 256, 1, true, 256>(views, ws, sz, ws.tile_order[blockIdx.x], t, S.quad, image, t_final, last_pos,
+                                    n_contrib, [](int tt, int, int &x, int &y) {
+                                      const int l = tt & 63, w = tt >> 6;
+                                      x = (w & 1) * 8 + (l & 7);
+                                      y = (w >> 1) * 8 + (l >> 3);
+                                    });
+  } else {
+    const uint32_t i = n_long + (blockIdx.x - n_long) * 4u + (uint32_t)wave_id();
+    if (i >= sz.t_tot) return;
+    fwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], image, t_final,
+                                   last_pos, n_contrib, [](int tt, int p, int &x, int &y) {
+                                     x = (tt & 7) + (p & 1) * 8;
+                                     y = (tt >> 3) + (p >> 1) * 8;
+                                   });
+  }
+}
+
+// 8 and 32 px tiles: one workgroup per tile (FwdTile), longest lists first.
+template <int TS>
+__global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *__restrict__ views, Ws ws,
+                                                                Sizes sz, float *__restrict__ image,
+                                                                float *__restrict__ t_final,
+                                                                uint32_t *__restrict__ last_pos,
+                                                                uint32_t *__restrict__ n_contrib) {
+  constexpr int NT = FwdTile<TS>::NT, PPT = FwdTile<TS>::PPT;
+  __shared__ FwdLds<NT> S;
+  if (ws.scalars[kOverflow]) return;
+  if (blockIdx.x >= sz.t_tot) return;
+  fwd_walk<TS, NT, PPT, true, NT>(views, ws, sz, ws.tile_order[blockIdx.x], threadIdx.x, S, image, t_final,
+                                  last_pos, n_contrib,
+                                  [](int tt, int p, int &x, int &y) { fwd_pixel<TS>(tt, p, x, y); });
 }
 
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
@@ -129,7 +203,8 @@ void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, flo
       k_raster_fwd<32><<<grid, FwdTile<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
       break;
     default:
-      k_raster_fwd<16><<<grid, FwdTile<16>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      // at most t_tot workgroups: one per long tile, then one per four tiles
+      k_raster_fwd16<<<sz.t_tot, 256, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
       break;
   }
 }

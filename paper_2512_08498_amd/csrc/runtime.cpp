@@ -42,7 +42,7 @@ struct gsr_ctx {
   float *loss_partials = nullptr;
   // tuning applied at the next gsr_plan
   int32_t tuned_ts = 16;
-  uint32_t long_list = 512;
+  uint32_t long_list = 1024;
   // stage timing
   bool prof = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

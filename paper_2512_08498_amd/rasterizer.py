@@ -45,7 +45,7 @@ class Rasterizer:
 
     def __init__(self, cams: Sequence, n: int, sh_degree: int, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
                  capacity_records: int = 0, capacity_pairs: int = 0, device="cuda", cams_device=None,
-                 long_list: int = 512):
+                 long_list: int = 1024):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -85,7 +85,7 @@ class Rasterizer:
         self._check(self.lib.gsr_get_tuning(self.ctx, C.byref(t)))
         return {"tile_size": t.tile_size, "long_list": t.long_list}
 
-    def set_tuning(self, tile_size, long_list=512):
+    def set_tuning(self, tile_size, long_list=1024):
         """Change the launch configuration and re-plan (same capacities)."""
         self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(int(tile_size), int(long_list), 0.0))))
         self.tile_size = int(tile_size)
