@@ -235,15 +235,8 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       }
       if (__ballot(any)) {
         const float v9[9] = {a_offx, a_offy, a_qa, a_qb, a_qc, a_o, a_r, a_g, a_b};
-        float t3[3];
-        wave_sum9(v9, t3);
-        if ((lane & 15) == 0) {
-          const int k = lane >> 4, i = 2 * (k & 1) + (k >> 1);
-          float *dst = L.g + ((size_t)jj * NW + wv) * 9;
-          dst[i] = t3[0];
-          dst[4 + i] = t3[1];
-          if (k == 0) dst[8] = t3[2];
-        }
+        const float sum = wave_sum9_packed(v9);  // value l in lane l < 8, value 8 in lane 32
+        if (lane < 8 || lane == 32) L.g[((size_t)jj * NW + wv) * 9 + (lane < 8 ? lane : 8)] = sum;
       }
     }
     group_sync<WG>();

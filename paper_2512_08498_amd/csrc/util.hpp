@@ -97,39 +97,45 @@ __device__ __forceinline__ float fold16(float x, float y) {
   return __uint_as_float(h[0]) + __uint_as_float(h[1]);
 }
 
-// Wave sums of nine values in a fixed order (deterministic).  On return,
-// lane 16k (k = 0..3) holds the sum of v[i(k)] in t[0] and of v[4 + i(k)]
-// in t[1], with i(k) = 2 (k & 1) + (k >> 1); lanes 0..15 hold the sum of v[8]
-// in t[2].  Every lane of the wave must be active.
-__device__ __forceinline__ void wave_sum9(const float (&v)[9], float (&t)[3]) {
-  float r[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) r[c] = row_sum16(v[c]);
-  const float s01 = fold32(r[0], r[1]), s23 = fold32(r[2], r[3]);
-  const float s45 = fold32(r[4], r[5]), s67 = fold32(r[6], r[7]);
-  const float s88 = fold32(r[8], r[8]);
-  t[0] = fold16(s01, s23);
-  t[1] = fold16(s45, s67);
-  t[2] = fold16(s88, s88);
+// keep + (send of the DPP partner CTRL), in float.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float keep, float send) {
+  return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes, in every lane: the row sums by four DPP steps,
-// then rows (0+2, 1+3) by a 32-lane swap and (0+1, 2+3) by a 16-lane swap.
-// Fixed order, so the result is deterministic; every lane must be active.
-__device__ __forceinline__ float wave_sum_all(float v) {
-  int x = __float_as_int(v);
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
-  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
-  const float s2 = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(s2), __float_as_uint(s2), false, false);
-  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+// Exchange-and-add of two values between DPP partners that differ in lane
+// bit `hi`: the lane with the bit clear keeps a, the other keeps b, and each
+// adds its partner's copy of the value it keeps.
+template <int CTRL>
+__device__ __forceinline__ float pack_add(float a, float b, bool hi) {
+  return dpp_add<CTRL>(hi ? b : a, hi ? a : b);
+}
+
+// Wave sums of nine values, with the values packed as the butterfly goes:
+// in-row steps xor 1, xor 2 (quad permutes) and rotate 4 each halve the
+// registers by keeping one value of a pair per lane (9 -> 5 -> 3 -> 2),
+// rotate 8 completes the row sums, and the 32- and 16-lane swaps add the
+// rows.  On return lane l < 8 holds the sum of v[l] and lanes 32..47 the sum
+// of v[8].  Fixed order (deterministic); every lane must be active.
+__device__ __forceinline__ float wave_sum9_packed(const float (&v)[9]) {
+  const int l = lane_id();
+  const bool b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1;
+  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor4 = 0x124, kRor8 = 0x128;
+  // xor 1: value 2k + b0 in register k
+  const float p0 = pack_add<kXor1>(v[0], v[1], b0), p1 = pack_add<kXor1>(v[2], v[3], b0);
+  const float p2 = pack_add<kXor1>(v[4], v[5], b0), p3 = pack_add<kXor1>(v[6], v[7], b0);
+  const float p4 = dpp_add<kXor1>(v[8], v[8]);
+  // xor 2: value 4k + 2 b1 + b0 in register k
+  const float q0 = pack_add<kXor2>(p0, p1, b1), q1 = pack_add<kXor2>(p2, p3, b1);
+  const float q2 = dpp_add<kXor2>(p4, p4);
+  // rotate 4: value 4 b2 + 2 b1 + b0 (= l & 7) in r0
+  const float r0 = pack_add<kRor4>(q0, q1, b2);
+  const float r1 = dpp_add<kRor4>(q2, q2);
+  // rotate 8: row sums
+  const float s0 = dpp_add<kRor8>(r0, r0), s1 = dpp_add<kRor8>(r1, r1);
+  // rows: s0 in lanes 0..31, s1 in lanes 32..63, then all four rows
+  const float f = fold32(s0, s1);
+  return fold16(f, f);
 }
 
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
