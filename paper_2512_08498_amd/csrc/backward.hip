@@ -55,11 +55,15 @@ __device__ __forceinline__ void view_dir(const Cam &c, const float m3[3], float 
   d[2] = ez * inv;
 }
 
+template <int NN>
+struct GroupN {
+  static constexpr int N = NN;
+};
+
 template <int DEG, bool ADAM>
 __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__restrict__ cams, Ws ws, Sizes sz,
                                                   MutPtrs grads, int accumulate, AdamArgs adam) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  constexpr int KC = 4;  // SH coefficients per chunk of the second pass
   if (ws.scalars[kOverflow]) return;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sz.n) return;
@@ -198,61 +202,82 @@ __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__rest
 
   float bc1 = 1.0f, bc2 = 1.0f;
   if (ADAM) bias_corrections(adam, bc1, bc2);
-  // write a gradient, or apply the Adam update to its parameter
-  auto emit = [&](float *p, float *m, float *v, float *gout, int64_t idx, float gval, float lr) {
+  // Gradients of a group of N parameters (pointer offsets off[i] from the
+  // group's arrays): written out, or applied by Adam with all loads of the
+  // group issued before any store, so the memory latency is paid once per
+  // group rather than once per parameter.
+  auto emit_group = [&](auto tag, float *p, float *m, float *v, float *gout, const int64_t(&off)[decltype(tag)::N],
+                        const float(&gv)[decltype(tag)::N], const float(&lr)[decltype(tag)::N]) {
+    constexpr int N = decltype(tag)::N;
     if (!ADAM) {
-      gout[idx] = accumulate ? gout[idx] + gval : gval;
+#pragma unroll
+      for (int i = 0; i < N; ++i) gout[off[i]] = accumulate ? gout[off[i]] + gv[i] : gv[i];
       return;
     }
-    float pp = p[idx], mm = m[idx], vv = v[idx];
-    adam_update(pp, mm, vv, gval, lr, adam.beta1, adam.beta2, adam.eps, bc1, bc2);
-    p[idx] = pp;
-    m[idx] = mm;
-    v[idx] = vv;
-    if (gout) gout[idx] = gval;
+    float pp[N], mm[N], vv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      pp[i] = p[off[i]];
+      mm[i] = m[off[i]];
+      vv[i] = v[off[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) adam_update(pp[i], mm[i], vv[i], gv[i], lr[i], adam.beta1, adam.beta2, adam.eps, bc1, bc2);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      p[off[i]] = pp[i];
+      m[off[i]] = mm[i];
+      v[off[i]] = vv[i];
+      if (gout) gout[off[i]] = gv[i];
+    }
   };
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    emit(adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, k * n + g, d_mean[k], adam.lr[0]);
-    emit(adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, k * n + g, d_l[k], adam.lr[1]);
+  {
+    const int64_t o3[3] = {g, n + g, 2 * n + g}, o4[4] = {g, n + g, 2 * n + g, 3 * n + g}, o1[1] = {g};
+    const float lr0[3] = {adam.lr[0], adam.lr[0], adam.lr[0]}, lr1[3] = {adam.lr[1], adam.lr[1], adam.lr[1]};
+    const float lr2[4] = {adam.lr[2], adam.lr[2], adam.lr[2], adam.lr[2]}, lr3[1] = {adam.lr[3]};
+    const float gth[1] = {d_theta};
+    emit_group(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, o3, d_mean, lr0);
+    emit_group(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, o3, d_l, lr1);
+    emit_group(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, o4, d_q, lr2);
+    emit_group(GroupN<1>{}, adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit,
+               o1, gth, lr3);
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) emit(adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, k * n + g, d_q[k], adam.lr[2]);
-  emit(adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit, g, d_theta,
-       adam.lr[3]);
 
-  // pass 2: SH coefficients, KC at a time (bounds the live registers)
+  // pass 2: SH coefficients, all K x 3 sums in one walk over the records
+  // (the geometry registers are dead by now), then the updates in groups of
+  // two coefficients (six parameters)
+  float a[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0f;
+  for (uint32_t r = r0; r < r1; ++r) {
+    const Cam c = load_cam(cams, (int)ws.rec_view[r]);
+    float cc[3], d[3], inv;
+    colour_cot(ws, r, cc);
+    view_dir(c, m3, d, inv);
+    float Y[16];
+    sh_basis(d[0], d[1], d[2], DEG, Y);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k][0] += Y[k] * cc[0];
+      a[k][1] += Y[k] * cc[1];
+      a[k][2] += Y[k] * cc[2];
+    }
+  }
+  constexpr int KC = K < 2 ? K : 2;
 #pragma unroll
   for (int kc = 0; kc < K; kc += KC) {
-    float a[KC][3];
+    int64_t off[3 * KC];
+    float gv[3 * KC], lr[3 * KC];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) a[kk][0] = a[kk][1] = a[kk][2] = 0.0f;
-    for (uint32_t r = r0; r < r1; ++r) {
-      const Cam c = load_cam(cams, (int)ws.rec_view[r]);
-      float cc[3], d[3], inv;
-      colour_cot(ws, r, cc);
-      view_dir(c, m3, d, inv);
-      float Y[16];
-      sh_basis(d[0], d[1], d[2], DEG, Y);
+    for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        if (kc + kk < K) {
-          a[kk][0] += Y[kc + kk] * cc[0];
-          a[kk][1] += Y[kc + kk] * cc[1];
-          a[kk][2] += Y[kc + kk] * cc[2];
-        }
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      if (kc + kk < K) {
+      for (int ch = 0; ch < 3; ++ch) {
         const int k = kc + kk;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-          emit(adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, ((int64_t)k * 3 + ch) * n + g, a[kk][ch],
-               k == 0 ? adam.lr[4] : adam.lr[5]);
+        off[3 * kk + ch] = ((int64_t)k * 3 + ch) * n + g;
+        gv[3 * kk + ch] = a[k][ch];
+        lr[3 * kk + ch] = k == 0 ? adam.lr[4] : adam.lr[5];
       }
-    }
+    emit_group(GroupN<3 * KC>{}, adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, off, gv, lr);
   }
 }
 
