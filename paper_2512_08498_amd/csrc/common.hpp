@@ -40,6 +40,7 @@ struct Ws {
   uint32_t *tile_count;     // [T_tot] list length        zeroed per forward
   uint32_t *tile_start;     // [T_tot] list start         zeroed per forward
   uint2 *block_sums;        // [n_blocks] (records, pairs) -> exclusive offsets
+  uint64_t *vis_mask;       // [vis_words][n] visible views of each Gaussian (bit v % 64 of word v / 64)
   uint32_t *rec_start;      // [n + 1] first record of each Gaussian
   float4 *rec_payload;      // [cap_rec][4] raster payload, see RecPayload
   uint32_t *rec_g;          // [cap_rec] Gaussian index
@@ -69,6 +70,7 @@ struct Sizes {
   uint32_t cap_pairs;
   uint32_t n_blocks;        // ceil(n / kPreBlock)
   uint32_t long_list;       // 16 px tiles: lists this long are walked by four waves in the backward
+  uint32_t vis_words;       // ceil(n_views / 64)
   float bg[3];
 };
 

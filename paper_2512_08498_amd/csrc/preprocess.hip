@@ -1,12 +1,13 @@
 // Preprocess: project every (view, Gaussian) pair, compact the visible ones
-// into records (Gaussian-major) with their tile rectangles and the offset of
-// their (record, tile) pairs.
+// into records (Gaussian-major) with their raster payload and tile
+// rectangles.
 //
 // Two passes over the Gaussians with a scan between them (reduce, then
 // scan, then write), so record indices are deterministic and increase with
 // the Gaussian index within each view -- the tie-break order of the sort.
-// Each thread owns one Gaussian and loops over all views, so its parameters
-// (236 bytes at SH degree 3) are read once per pass for the whole batch.
+// Each thread owns one Gaussian: the counting pass projects it into every
+// view and keeps a bit mask of the views that see it; the writing pass
+// projects it again only into those views.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -35,6 +36,7 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_count(GaussPtrs gp, const Cam
   if (g < sz.n) {
     float m3[3], l3[3], q4[4];
     load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+    uint64_t word = 0;
     for (int v = 0; v < sz.n_views; ++v) {
       const Cam c = load_cam(cams, v);
       Proj P;
@@ -42,6 +44,11 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_count(GaussPtrs gp, const Cam
       if (P.visible) {
         recs += 1;
         pairs += rect_area(P, ts_shift);
+        word |= uint64_t(1) << (v & 63);
+      }
+      if ((v & 63) == 63 || v == sz.n_views - 1) {
+        ws.vis_mask[(int64_t)(v >> 6) * sz.n + g] = word;
+        word = 0;
       }
     }
   }
@@ -88,24 +95,13 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
   if (ws.scalars[kOverflow]) return;
   const int64_t g = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   const bool live = g < sz.n;
-  float m3[3], l3[3], q4[4];
-  uint32_t recs = 0, pairs = 0;
-  if (live) {
-    load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
-    for (int v = 0; v < sz.n_views; ++v) {
-      const Cam c = load_cam(cams, v);
-      Proj P;
-      project_spec(m3, l3, q4, c, P);
-      if (P.visible) {
-        recs += 1;
-        pairs += rect_area(P, ts_shift);
-      }
-    }
-  }
-  uint32_t tr, tp;
+  // the visible views from the counting pass: only those are projected again
+  uint32_t recs = 0;
+  if (live)
+    for (uint32_t w = 0; w < sz.vis_words; ++w) recs += (uint32_t)__popcll(ws.vis_mask[(int64_t)w * sz.n + g]);
+  uint32_t tr;
   const uint2 base = ws.block_sums[blockIdx.x];
   uint32_t rec = base.x + block_excl_scan<kPreBlock>(recs, s_scan, tr);
-  uint32_t pair = base.y + block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
   if (!live) return;
   ws.rec_start[g] = rec;
   if (g == sz.n - 1) ws.rec_start[sz.n] = rec + recs;
@@ -118,11 +114,14 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
     for (int ch = 0; ch < 3; ++ch) sh[k][ch] = gp.sh[((int64_t)k * 3 + ch) * sz.n + g];
   const float op = 1.0f / (1.0f + expf(-gp.opacity_logit[g]));
 
-  for (int v = 0; v < sz.n_views; ++v) {
+  float m3[3], l3[3], q4[4];
+  load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+  for (uint32_t wd = 0; wd < sz.vis_words; ++wd)
+    for (uint64_t bits = ws.vis_mask[(int64_t)wd * sz.n + g]; bits; bits &= bits - 1) {
+    const int v = (int)(wd * 64u) + __ffsll((unsigned long long)bits) - 1;
     const Cam c = load_cam(cams, v);
     Proj P;
     project_spec(m3, l3, q4, c, P);
-    if (!P.visible) continue;
     // 2D mean in float64 (the pixel grid is ~2^11 wide, so a float32
     // projection would be off by up to ~1e-4 px); stored as the offset from
     // the box corner, which float32 represents to ~1e-7 px.
@@ -172,11 +171,9 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
     const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
     ws.rec_g[rec] = (uint32_t)g;
     ws.rec_view[rec] = (uint32_t)v;
-    ws.rec_pairoff[rec] = pair;
     ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
     ws.rec_zbits[rec] = P.zbits;
     rec += 1;
-    pair += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   }
 }
 

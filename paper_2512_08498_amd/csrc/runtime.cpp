@@ -19,7 +19,7 @@ namespace {
 
 struct Layout {
   size_t scalars, tile_count, tile_start, zero_end;
-  size_t block_sums, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
+  size_t block_sums, vis_mask, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
   size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d;
   size_t total;
 };
@@ -95,6 +95,7 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   Ws w;
   w.scalars = reinterpret_cast<uint32_t *>(b + L.scalars);
   w.block_sums = reinterpret_cast<uint2 *>(b + L.block_sums);
+  w.vis_mask = reinterpret_cast<uint64_t *>(b + L.vis_mask);
   w.rec_start = reinterpret_cast<uint32_t *>(b + L.rec_start);
   w.rec_payload = reinterpret_cast<float4 *>(b + L.payload);
   w.rec_g = reinterpret_cast<uint32_t *>(b + L.rec_g);
@@ -134,6 +135,7 @@ Layout make_layout(const Sizes &s) {
   put(L.tile_start, (size_t)s.t_tot * 4);
   L.zero_end = o;
   put(L.block_sums, (size_t)s.n_blocks * 8);
+  put(L.vis_mask, (size_t)s.vis_words * (size_t)s.n * 8);
   put(L.rec_start, (size_t)(s.n + 1) * 4);
   put(L.payload, (size_t)s.cap_rec * 64);
   put(L.rec_g, (size_t)s.cap_rec * 4);
@@ -272,6 +274,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   s.cap_pairs = (uint32_t)cap_pairs;
   s.n_blocks = (uint32_t)((n + kPreBlock - 1) / kPreBlock);
   s.long_list = c->long_list;
+  s.vis_words = (uint32_t)((n_views + 63) / 64);
   for (int k = 0; k < 3; ++k) s.bg[k] = opt ? opt->bg[k] : 0.0f;
   c->views = views;
   c->sz = s;
