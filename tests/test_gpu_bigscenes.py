@@ -1,0 +1,185 @@
+"""Parity at full size on the single 1920x1080 view with 500k Gaussians and
+on the street scene of 24 views at 1920x1080 with 6M Gaussians (16 px
+tiles), on outputs the oracle computes one by one: binning of whole views
+bit for bit, sampled pixels, gradients under a loss on pixel windows, and on
+the 1080p view the gradients of a 200-Gaussian subset against the FP64
+oracle and its central differences."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import grads_to_host, host_outputs, last_gaussian, log
+from oracle.binning import tile_lists
+from oracle.fd import fd_gradient
+from oracle.grad64 import grad64
+from oracle.render64 import render_pixels, render_view, view_setup
+from paper_2512_08498_amd import Rasterizer
+from workloads import make_config, make_target
+
+pytestmark = pytest.mark.gpu
+
+TS = 16
+
+
+def _setup(cfg, cap_rec, cap_pairs):
+    scene, cams = make_config(cfg)
+    params = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in scene.arrays().items()}
+    rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=TS, capacity_records=cap_rec,
+                      capacity_pairs=cap_pairs)
+    out = rast.forward(params)  # re-plans on a capacity overflow
+    torch.cuda.synchronize()
+    rec, pairs, tiles = rast.required_capacity()
+    log(f"config {cfg}: {scene.n} Gaussians, {len(cams)} views, records {rec}, pairs {pairs}, tiles {tiles}")
+    return scene, cams, rast, params, out
+
+
+@pytest.fixture(scope="module")
+def view1080():
+    return _setup(2, 1_000_000, 4_000_000)
+
+
+@pytest.fixture(scope="module")
+def street():
+    return _setup(5, 30_000_000, 80_000_000)
+
+
+def _tile_base(rast, v):
+    base = 0
+    for w, h in rast.sizes[:v]:
+        base += ((w + TS - 1) // TS) * ((h + TS - 1) // TS)
+    w, h = rast.sizes[v]
+    return base, ((w + TS - 1) // TS) * ((h + TS - 1) // TS)
+
+
+def _check_binning(scene, cams, rast, views):
+    keys, vals, csr = rast.debug_binning()
+    for v in views:
+        base, nt = _tile_base(rast, v)
+        lo, hi = int(csr[base]), int(csr[base + nt])
+        okeys, ovals, ocsr = tile_lists(scene, [cams[v]], TS)
+        log(f"view {v}: {hi - lo} pairs")
+        assert hi - lo == len(okeys)
+        assert np.array_equal(keys[lo:hi] - (np.uint64(base) << np.uint64(32)), okeys)
+        assert np.array_equal(vals[lo:hi], ovals)
+        assert np.array_equal(csr[base:base + nt + 1] - lo, ocsr)
+
+
+def _check_pixels(scene, cams, rast, out, views, per_view, seed):
+    keys, vals, csr = rast.debug_binning()
+    imgs, T, cnt, last = host_outputs(rast, out)
+    rng = np.random.default_rng(seed)
+    arrays = scene.arrays()
+    checked = 0
+    for v in views:
+        c = cams[v]
+        setup = view_setup(arrays, scene.sh_degree, c)
+        pix = [(int(rng.integers(0, c.width)), int(rng.integers(0, c.height))) for _ in range(per_view)]
+        pix += [(c.width - 1, c.height - 1), (c.width // 2, c.height // 2)]
+        ref = render_pixels(arrays, scene.sh_degree, c, pix, setup=setup)
+        lg = last_gaussian(rast, last[v], v, vals, csr)
+        for (i, j), r in zip(pix, ref):
+            if r["ambiguous"]:
+                continue
+            assert np.abs(imgs[v][:, j, i] - r["color"]).max() <= 1e-5, (v, i, j)
+            assert abs(T[v][j, i] - r["T"]) <= 1e-5
+            assert cnt[v][j, i] == r["count"] and lg[j, i] == r["last"], (v, i, j)
+            checked += 1
+    return checked
+
+
+def _check_window_gradients(scene, cams, rast, params, out, cfg, wins):
+    targets = make_target(cfg, cams)
+    arrays = scene.arrays()
+    total_px = rast.total_px
+    cots = {}
+    for v, (x0, x1, y0, y1) in wins.items():
+        fwd = render_view(arrays, scene.sh_degree, cams[v], window=(x0, x1, y0, y1))
+        g = np.zeros((3, cams[v].height, cams[v].width), np.float32)
+        gw = np.sign(fwd["image"] - targets[v][:, y0:y1, x0:x1]) / (3.0 * total_px)
+        gw[:, fwd["ambiguous"]] = 0.0
+        g[:, y0:y1, x0:x1] = gw
+        cots[v] = g
+    dl = torch.zeros(3 * total_px, dtype=torch.float32, device="cuda")
+    for v in wins:
+        dl[3 * rast.pix_off[v]:3 * rast.pix_off[v + 1]] = torch.from_numpy(cots[v].reshape(-1)).cuda()
+    gpu = grads_to_host(rast.backward(params, out, dl))
+    ref = grad64(scene, [cams[v] for v in wins], [cots[v].astype(np.float64) for v in wins],
+                 windows=[wins[v] for v in wins])
+    for k in ref:
+        scale = np.abs(ref[k]).max()
+        diff = np.abs(gpu[k] - ref[k])
+        big = np.abs(ref[k]) >= 1e-2 * scale
+        rel = (diff[big] / np.abs(ref[k][big])).max()
+        log(f"  grad {k}: {diff.max() / scale:.2e} of max, rel {rel:.2e}")
+        assert diff.max() <= 1e-4 * scale, k
+        assert rel <= 1e-4, k
+
+
+def test_view1080_binning_bit_exact(view1080):
+    scene, cams, rast, params, out = view1080
+    _check_binning(scene, cams, rast, [0])
+
+
+def test_view1080_sampled_pixels(view1080):
+    scene, cams, rast, params, out = view1080
+    assert _check_pixels(scene, cams, rast, out, [0], 60, 2002) >= 55
+
+
+def test_view1080_window_gradients(view1080):
+    scene, cams, rast, params, out = view1080
+    _check_window_gradients(scene, cams, rast, params, out, 2, {0: (944, 976, 524, 556)})
+
+
+def test_view1080_subset_gradients_against_oracle_and_fd(view1080):
+    """200 visible Gaussians of the 1080p scene rendered alone at full
+    resolution: every gradient against the FP64 oracle, and 60 sampled
+    parameters against its central differences."""
+    scene, cams, _, _, _ = view1080
+    spec, order, _ = view_setup(scene.arrays(), scene.sh_degree, cams[0])
+    rng = np.random.default_rng(2200)
+    sub = scene.subset(np.sort(rng.choice(order, 200, replace=False)))
+    params = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in sub.arrays().items()}
+    rast = Rasterizer(cams, sub.n, sub.sh_degree, tile_size=TS)
+    out = rast.forward(params)
+    cot = rng.standard_normal((3, cams[0].height, cams[0].width)) * 1e-3
+    oracle = render_view(sub.arrays(), sub.sh_degree, cams[0])
+    cot[:, oracle["ambiguous"]] = 0.0
+    dl = torch.from_numpy(cot.astype(np.float32).reshape(-1)).cuda()
+    gpu = grads_to_host(rast.backward(params, out, dl))
+    ref = grad64(sub, cams, [cot])
+    for k in ref:
+        scale = np.abs(ref[k]).max()
+        diff = np.abs(gpu[k] - ref[k])
+        big = np.abs(ref[k]) >= 1e-2 * scale
+        rel = (diff[big] / np.abs(ref[k][big])).max()
+        log(f"  grad {k}: {diff.max() / scale:.2e} of max, rel {rel:.2e}")
+        assert diff.max() <= 1e-4 * scale, k
+        assert rel <= 1e-4, k
+    checked = 0
+    for name in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
+        flat = ref[name].reshape(-1)
+        for idx in rng.choice(flat.size, 12, replace=False):
+            fd, valid = fd_gradient(sub, cams, [cot], name, int(idx))
+            if not valid:
+                continue
+            g = float(gpu[name].reshape(-1)[idx])
+            tol = 1e-4 * max(np.abs(flat).max(), 1e-12) + 1e-3 * abs(fd)
+            assert abs(g - fd) <= tol, (name, int(idx), g, fd)
+            checked += 1
+    log(f"{checked} parameters checked by central differences")
+    assert checked >= 40
+
+
+def test_street_binning_bit_exact(street):
+    scene, cams, rast, params, out = street
+    _check_binning(scene, cams, rast, [0, 13, 23])
+
+
+def test_street_sampled_pixels(street):
+    scene, cams, rast, params, out = street
+    assert _check_pixels(scene, cams, rast, out, [0, 23], 25, 5005) >= 45
+
+
+def test_street_window_gradients(street):
+    scene, cams, rast, params, out = street
+    _check_window_gradients(scene, cams, rast, params, out, 5, {0: (944, 976, 524, 556), 23: (300, 332, 700, 732)})
