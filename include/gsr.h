@@ -195,7 +195,7 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, void *workspace, uint64_t *keys, uint
 /* Compositing work of the last forward, for roofline accounting: writes to
  * *evals (DEVICE, one uint64) the number of (pixel, list entry) pairs with
  * the entry in front of the pixel's stop position fwd->last_pos and the
- * pixel inside the entry's pixel box (Sec. 3.3 compositing order), summed
+ * pixel inside the entry's binning box (Sec. 3.3 compositing order), summed
  * over all pixels of all views.  These are the evaluations the backward
  * performs; the forward performs the same plus the entries between a
  * pixel's last composited Gaussian and its stop.  Reads the workspace and

@@ -88,12 +88,15 @@ constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 0x1.715476p+0f;
 constexpr float kHalfLog2e = 0x1.715476p-1f;   // log2(e) / 2
 
-// Raster payload of one record, four float4 (64 bytes, read by the
-// compositing kernels through the scalar cache):
-//  p0 = (i0, i1, j0, j1)            inclusive pixel box, as floats
-//  p1 = (offx, offy, qa, qb)        mean offset from the box corner; conic
+// Raster payload of one record, four float4 (64 bytes, staged in LDS by the
+// compositing kernels):
+//  p0 = (i0, i1, j0, j1)            inclusive pixel box the compositing tests,
+//                                   as floats: the binning box narrowed to
+//                                   d^2 <= 2 ln(255 opacity) (empty if the
+//                                   opacity is below 1/255)
+//  p1 = (offx, offy, qa, qb)        mean offset from that box's corner; conic
 //  p2 = (qc, opacity, r, g)         in Cholesky form (see raster.hpp)
-//  p3 = (b, i0 | i1 << 16, j0 | j1 << 16, pass)   the box again, as packed
+//  p3 = (b, i0 | i1 << 16, j0 | j1 << 16, pass)   the binning box, as packed
 //                                   16-bit integers, and bits 0..2 set where
 //                                   colour channel ch was not clamped at 0
 //                                   (bit patterns)

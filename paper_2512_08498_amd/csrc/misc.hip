@@ -89,10 +89,10 @@ void launch_debug_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, 
 }
 
 // Compositing work of the last forward: for every pixel, the entries of its
-// tile's list in front of its stop position (last_pos) whose pixel box
-// contains the pixel.  These are the (pixel, Gaussian) evaluations the
-// backward must perform; the forward performs these plus the few entries
-// between last_pos and its stop.  One workgroup per tile, boxes staged in
+// tile's list in front of its stop position (last_pos) whose binning box
+// contains the pixel -- the (pixel, Gaussian) evaluations of the method's
+// definition.  The compositing kernels skip the pixels outside a record's
+// opacity-narrowed box, where alpha < 1/255, so they perform fewer.  One workgroup per tile, boxes staged in
 // LDS; a per-workgroup integer sum is added to *evals.
 __global__ __launch_bounds__(256) void k_count_evals(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
                                                      const uint32_t *__restrict__ last_pos,
@@ -127,7 +127,11 @@ __global__ __launch_bounds__(256) void k_count_evals(const ViewInfo *__restrict_
     if (threadIdx.x < m) {
       uint32_t rec = ws.tile_recs[start + b0 + threadIdx.x];
       if (rec >= nrec) rec = 0;
-      s_box[threadIdx.x] = ws.rec_payload[(size_t)rec * 4];
+      // the binning box (p3, packed): evaluations are counted against it
+      const float4 p3 = ws.rec_payload[(size_t)rec * 4 + 3];
+      const uint32_t bx = __float_as_uint(p3.y), by = __float_as_uint(p3.z);
+      s_box[threadIdx.x] = make_float4((float)(bx & 0xFFFFu), (float)(bx >> 16), (float)(by & 0xFFFFu),
+                                       (float)(by >> 16));
     }
     __syncthreads();
     for (uint32_t j = 0; j < m; ++j) {

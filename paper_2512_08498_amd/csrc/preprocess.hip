@@ -128,8 +128,28 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
     const double xd = ((double)c.R[0] * m3[0] + (double)c.R[1] * m3[1]) + (double)c.R[2] * m3[2] + c.t[0];
     const double yd = ((double)c.R[3] * m3[0] + (double)c.R[4] * m3[1]) + (double)c.R[5] * m3[2] + c.t[1];
     const double zd = ((double)c.R[6] * m3[0] + (double)c.R[7] * m3[1]) + (double)c.R[8] * m3[2] + c.t[2];
-    const float offx = (float)((double)c.fx * (xd / zd) + (double)c.cx - (double)P.i0 - 0.5);
-    const float offy = (float)((double)c.fy * (yd / zd) + (double)c.cy - (double)P.j0 - 0.5);
+    const double mux = (double)c.fx * (xd / zd) + (double)c.cx, muy = (double)c.fy * (yd / zd) + (double)c.cy;
+    // The compositing kernels test the box of d^2 <= 2 ln(255 opacity)
+    // instead of the binning box: outside it alpha < 1/255 (for a pixel
+    // centre dx from the mean, d^2 >= dx^2 / S_xx), so the same entries are
+    // composited.  The 0.01 margin in d^2 covers the rounding of the kernels'
+    // d^2 and of this box.  The binning (tile lists) keeps the full box.
+    float bi0 = (float)P.i0, bi1 = (float)P.i1, bj0 = (float)P.j0, bj1 = (float)P.j1;
+    const float keff = 2.0f * logf(255.0f * op) + 0.01f;
+    if (keff < kSupportK) {
+      if (!(keff > 0.0f)) {  // opacity below 1/255: nothing can composite
+        bi0 = bj0 = 1.0f;
+        bi1 = bj1 = 0.0f;
+      } else {
+        const float hxt = sqrtf(keff * (P.p0 + kDilation)), hyt = sqrtf(keff * (P.p1 + kDilation));
+        bi0 = fmaxf(bi0, ceilf((float)mux - hxt - 0.5f));
+        bi1 = fminf(bi1, floorf((float)mux + hxt - 0.5f));
+        bj0 = fmaxf(bj0, ceilf((float)muy - hyt - 0.5f));
+        bj1 = fminf(bj1, floorf((float)muy + hyt - 0.5f));
+      }
+    }
+    const float offx = (float)(mux - (double)bi0 - 0.5);
+    const float offy = (float)(muy - (double)bj0 - 0.5);
     // Conic in Cholesky form.  With S = A A^T + 0.3 I:
     //   d^T S^-1 d = (dx + qb dy)^2 * S_yy / det + dy^2 / S_yy,  qb = -S_xy / S_yy
     // and det = |a0 x a1|^2 + 0.3 (|a0|^2 + |a1|^2) + 0.09 has no cancellation.
@@ -161,7 +181,7 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
       rgb[ch] = fmaxf(s, 0.0f);
       pass |= (s >= 0.0f ? 1u : 0u) << ch;
     }
-    ws.rec_payload[(size_t)rec * 4 + 0] = make_float4((float)P.i0, (float)P.i1, (float)P.j0, (float)P.j1);
+    ws.rec_payload[(size_t)rec * 4 + 0] = make_float4(bi0, bi1, bj0, bj1);
     ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
     ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
     ws.rec_payload[(size_t)rec * 4 + 3] =
