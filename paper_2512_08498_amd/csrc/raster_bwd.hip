@@ -319,10 +319,18 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *
 
 // Sum each record's per-tile partials (contiguous, record-major) into its
 // reduced gradient.  Each wave takes 64 consecutive records: a lane sums a
-// record of at most kBig pairs alone; larger footprints are summed by the
-// whole wave (lane l takes pairs l, l + 64, ...) and reduced with DPP, so a
-// record covering thousands of tiles does not stall its wave.
-constexpr uint32_t kBig = 64;
+// record of at most kBig pairs alone, two pairs per step so their loads
+// overlap; larger footprints are summed by the whole wave (lane l takes
+// pairs l, l + 64, ...) and reduced across lanes, so one big record does not
+// hold its wave for hundreds of dependent loads.
+constexpr uint32_t kBig = 16;
+
+__device__ __forceinline__ void add_partial(const float4 *__restrict__ src, float (&v)[9]) {
+  const float4 x = src[0], y = src[1], z = src[2];
+  v[0] += x.x; v[1] += x.y; v[2] += x.z; v[3] += x.w;
+  v[4] += y.x; v[5] += y.y; v[6] += y.z; v[7] += y.w;
+  v[8] += z.x;
+}
 
 __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws) {
   if (ws.scalars[kOverflow]) return;
@@ -339,17 +347,20 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws) {
       p0 = ws.rec_pairoff[r];
     }
     if (r < nrec && cnt <= kBig) {
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
-      for (uint32_t k = 0; k < cnt; ++k) {
-        const float4 *src = ws.partials + (size_t)(p0 + k) * 3;
-        const float4 x = src[0], y = src[1], z = src[2];
-        a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
-        b.x += y.x; b.y += y.y; b.z += y.z; b.w += y.w;
-        c.x += z.x;
+      float a[9], b[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a[k] = b[k] = 0.0f;
+      uint32_t k = 0;
+      for (; k + 1 < cnt; k += 2) {
+        add_partial(ws.partials + (size_t)(p0 + k) * 3, a);
+        add_partial(ws.partials + (size_t)(p0 + k + 1) * 3, b);
       }
-      ws.g2d[(size_t)r * 3 + 0] = a;
-      ws.g2d[(size_t)r * 3 + 1] = b;
-      ws.g2d[(size_t)r * 3 + 2] = c;
+      if (k < cnt) add_partial(ws.partials + (size_t)(p0 + k) * 3, a);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) a[c] += b[c];
+      ws.g2d[(size_t)r * 3 + 0] = make_float4(a[0], a[1], a[2], a[3]);
+      ws.g2d[(size_t)r * 3 + 1] = make_float4(a[4], a[5], a[6], a[7]);
+      ws.g2d[(size_t)r * 3 + 2] = make_float4(a[8], 0.0f, 0.0f, 0.0f);
     }
     uint64_t big = __ballot(r < nrec && cnt > kBig);
     while (big) {
@@ -359,20 +370,13 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws) {
       float v[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-      for (uint32_t k = lane; k < bc; k += kWave) {
-        const float4 *src = ws.partials + (size_t)(bp + k) * 3;
-        const float4 x = src[0], y = src[1], z = src[2];
-        v[0] += x.x; v[1] += x.y; v[2] += x.z; v[3] += x.w;
-        v[4] += y.x; v[5] += y.y; v[6] += y.z; v[7] += y.w;
-        v[8] += z.x;
-      }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
-      if (lane == kWave - 1) {
-        const size_t rr = (size_t)(wbase + l) * 3;
-        ws.g2d[rr + 0] = make_float4(v[0], v[1], v[2], v[3]);
-        ws.g2d[rr + 1] = make_float4(v[4], v[5], v[6], v[7]);
-        ws.g2d[rr + 2] = make_float4(v[8], 0.0f, 0.0f, 0.0f);
+      for (uint32_t k = lane; k < bc; k += kWave) add_partial(ws.partials + (size_t)(bp + k) * 3, v);
+      const float sum = wave_sum9_packed(v);  // value l in lane l < 8, value 8 in lane 32
+      float *dst = reinterpret_cast<float *>(ws.g2d + (size_t)(wbase + l) * 3);
+      if (lane < 8) dst[lane] = sum;
+      if (lane == 32) {
+        dst[8] = sum;
+        dst[9] = dst[10] = dst[11] = 0.0f;
       }
     }
   }

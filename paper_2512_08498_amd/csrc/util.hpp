@@ -68,20 +68,6 @@ __device__ __forceinline__ T wave_reduce_max(T x) {
 
 // Sum over the wave with DPP row operations; the total is valid in lane 63.
 // Must be called with all 64 lanes active.
-// Sum over each row of 16 lanes, in every lane of the row (four DPP steps).
-__device__ __forceinline__ float row_sum16(float v) {
-  int x = __float_as_int(v);
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
-  return __int_as_float(x);
-}
-
 // Swap-and-add of two row-summed values a, b: lanes 0..31 get
 // a[l] + a[l + 32], lanes 32..63 get b[l - 32] + b[l].
 __device__ __forceinline__ float fold32(float a, float b) {
@@ -138,25 +124,6 @@ __device__ __forceinline__ float wave_sum9_packed(const float (&v)[9]) {
   return fold16(f, f);
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-  int x = __float_as_int(v);
-  // quad butterflies: lanes (0,1,2,3) -> (1,0,3,2) then (2,3,0,1)
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false)));
-  // rotate within each row of 16 by 4, then by 8: every lane holds its row sum
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false)));
-  // row broadcasts: lane 15 of rows 0/2 into rows 1/3, then lane 31 into rows 2/3
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false)));
-  x = __float_as_int(__int_as_float(x) +
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false)));
-  return __int_as_float(x);
-}
 
 // Lanes below this one in the wave.
 __device__ __forceinline__ uint64_t lanemask_lt() { return (uint64_t(1) << lane_id()) - 1u; }
