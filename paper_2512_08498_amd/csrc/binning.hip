@@ -48,11 +48,14 @@ __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t 
   return count_dev ? min(*count_dev, cap) : cap;
 }
 
-// Emission: each wave expands 64 consecutive records of the depth order
-// into their pairs: lane l takes pair b + l of the wave's concatenated tile
-// rectangles and finds its record by a binary search over the wave's prefix
-// sums, so a big footprint is spread over the lanes.  offs[i] is the first
-// pair of sorted record i; it is also kept per record for the backward.
+// Emission: each wave takes 64 consecutive records of the depth order; their
+// pairs form one contiguous range (offs[i] is the first pair of sorted record
+// i, kept per record for the backward).  A record of at most kEmitSmall pairs
+// is written by its own lane, stepping through its tile rectangle; the lanes'
+// stores fall into that one range.  Bigger footprints are written by the
+// whole wave, 64 pairs per step.
+constexpr uint32_t kEmitSmall = 8;
+
 __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
                                               const uint32_t *__restrict__ perm, const uint32_t *__restrict__ offs,
                                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
@@ -63,45 +66,47 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
   for (uint32_t wbase = (blockIdx.x * (blockDim.x / kWave) + wave_id()) * kWave; wbase < nrec;
        wbase += wave_stride) {
     const uint32_t i = wbase + lane;
-    uint32_t tx0 = 0, w = 1, ty0 = 0, cnt = 0, off = 0, rec = 0, tbase = 0, tpitch = 0;
+    uint32_t tx0 = 0, tx1 = 0, ty0 = 0, w = 1, cnt = 0, off = 0, rec = 0, tbase = 0, tpitch = 0;
     if (i < nrec) {
       rec = perm[i];
       const uint2 rc = ws.rec_rect[rec];
       tx0 = rc.x & 0xFFFFu;
-      w = (rc.x >> 16) - tx0 + 1;
+      tx1 = rc.x >> 16;
       ty0 = rc.y & 0xFFFFu;
+      w = tx1 - tx0 + 1;
       cnt = w * ((rc.y >> 16) - ty0 + 1);
       const ViewInfo vi = views[ws.rec_view[rec]];
       tbase = vi.tile_base;
       tpitch = (uint32_t)vi.tiles_x;
       off = offs[i];
       ws.rec_pairoff[rec] = off;
-    }
-    const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t excl = incl - cnt;
-    const uint32_t total = __shfl(incl, kWave - 1, kWave);
-    for (uint32_t b = 0; b < total; b += kWave) {
-      const uint32_t p = b + lane;
-      int o = 0;
-#pragma unroll
-      for (int s = 32; s >= 1; s >>= 1) {
-        const uint32_t e = __shfl(excl, o + s, kWave);
-        if (e <= p) o += s;
+      if (off + cnt > sz.cap_pairs) {  // inconsistent pair offsets
+        ws.scalars[kOverflow] = 3u;
+        cnt = 0;
       }
-      const uint32_t o_tx0 = __shfl(tx0, o, kWave), o_w = __shfl(w, o, kWave);
-      const uint32_t o_ty0 = __shfl(ty0, o, kWave), o_ex = __shfl(excl, o, kWave);
-      const uint32_t o_off = __shfl(off, o, kWave), o_rec = __shfl(rec, o, kWave);
-      const uint32_t o_base = __shfl(tbase, o, kWave), o_pitch = __shfl(tpitch, o, kWave);
-      if (p < total) {
-        const uint32_t k = p - o_ex;
-        const uint32_t tx = o_tx0 + k % o_w, ty = o_ty0 + k / o_w;
-        const uint32_t pos = o_off + k;
-        if (pos < sz.cap_pairs) {
-          keys[pos] = o_base + ty * o_pitch + tx;
-          vals[pos] = o_rec;
-        } else {
-          ws.scalars[kOverflow] = 3u;  // inconsistent pair offsets
+    }
+    if (cnt <= kEmitSmall) {
+      uint32_t tx = tx0, row = tbase + ty0 * tpitch;
+      for (uint32_t k = 0; k < cnt; ++k) {
+        keys[off + k] = row + tx;
+        vals[off + k] = rec;
+        if (++tx > tx1) {
+          tx = tx0;
+          row += tpitch;
         }
+      }
+    }
+    uint64_t big = __ballot(cnt > kEmitSmall);
+    while (big) {
+      const int l = __ffsll((unsigned long long)big) - 1;
+      big &= big - 1;
+      const uint32_t b_cnt = __shfl(cnt, l, kWave), b_off = __shfl(off, l, kWave), b_rec = __shfl(rec, l, kWave);
+      const uint32_t b_tx0 = __shfl(tx0, l, kWave), b_w = __shfl(w, l, kWave);
+      const uint32_t b_row0 = __shfl(tbase + ty0 * tpitch, l, kWave), b_pitch = __shfl(tpitch, l, kWave);
+      for (uint32_t k = lane; k < b_cnt; k += kWave) {
+        const uint32_t r = k / b_w, c = k - r * b_w;
+        keys[b_off + k] = b_row0 + r * b_pitch + b_tx0 + c;
+        vals[b_off + k] = b_rec;
       }
     }
   }
@@ -350,18 +355,35 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
 // 3. List bounds from the sorted tile ids: the first entry of a tile writes
 // its start, the last one its end (into tile_count, turned into the length
 // by k_tile_classify).  Both arrays are zeroed by the forward beforehand.
+// Each thread takes four consecutive ids with one 16-byte load.
 __global__ void k_tile_bounds(Ws ws, Sizes sz, const uint32_t *__restrict__ tiles) {
   if (ws.scalars[kOverflow]) return;
   const uint32_t n = min(ws.scalars[kNumPairs], sz.cap_pairs);
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t t = tiles[i];
-    if (t >= sz.t_tot) {
-      ws.scalars[kOverflow] = 3u;
-      continue;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; 4 * q < n; q += stride) {
+    const uint32_t i0 = 4 * q;
+    uint32_t t[6];
+    t[0] = i0 > 0 ? tiles[i0 - 1] : 0xFFFFFFFFu;
+    if (i0 + 4 <= n) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(tiles + i0);  // i0 is a multiple of 4
+      t[1] = v.x; t[2] = v.y; t[3] = v.z; t[4] = v.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[1 + k] = i0 + k < n ? tiles[i0 + k] : 0xFFFFFFFFu;
     }
-    if (i == 0 || tiles[i - 1] != t) ws.tile_start[t] = i;
-    if (i == n - 1 || tiles[i + 1] != t) ws.tile_count[t] = i + 1;
+    t[5] = i0 + 4 < n ? tiles[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      const uint32_t i = i0 + (uint32_t)k - 1;
+      if (i >= n) break;
+      const uint32_t tl = t[k];
+      if (tl >= sz.t_tot) {
+        ws.scalars[kOverflow] = 3u;
+        continue;
+      }
+      if (t[k - 1] != tl) ws.tile_start[tl] = i;
+      if (t[k + 1] != tl) ws.tile_count[tl] = i + 1;
+    }
   }
 }
 
