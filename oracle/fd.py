@@ -13,6 +13,7 @@ quotient is not a derivative and the parameter is reported invalid.
 from __future__ import annotations
 
 import numpy as np
+import torch
 
 from .grad64 import vjp_value
 from .project64 import to_params64
@@ -62,6 +63,30 @@ def fd_gradient(scene, cams, cotangents, name, flat_index, h_rel=1e-6, bg=(0.0, 
     vals, sigs = [], []
     for p in states:
         v, s = vjp_value(arrays, scene.sh_degree, cams_a, cots_a, p, bg=bg, windows=wins_a)
+        vals.append(v)
+        sigs.append(s)
+    valid = sigs[0] == sigs[1] == sigs[2]
+    return (vals[2] - vals[0]) / (2.0 * h), valid
+
+
+def fd_pose_gradient(scene, cams, cotangents, view, entry, h=1e-6, bg=(0.0, 0.0, 0.0)):
+    """Central difference of Phi with respect to entry ``entry`` (0..8: R
+    row-major, 9..11: t) of view ``view``'s pose, perturbed in FP64 in the
+    geometry x_c = R mu + t only (the SH direction and the FP32 binning
+    decisions stay those of the camera).  Returns (value, valid) as above."""
+    arrays = scene.arrays()
+    base = to_params64(arrays)
+    cam = cams[view]
+    R0 = torch.from_numpy(np.ascontiguousarray(np.asarray(cam.R, np.float32), np.float64).reshape(3, 3))
+    t0 = torch.from_numpy(np.ascontiguousarray(np.asarray(cam.t, np.float32), np.float64).reshape(3))
+    vals, sigs = [], []
+    for delta in (-h, 0.0, h):
+        R, t = R0.clone(), t0.clone()
+        if entry < 9:
+            R.reshape(-1)[entry] += delta
+        else:
+            t[entry - 9] += delta
+        v, s = vjp_value(arrays, scene.sh_degree, [cam], [cotangents[view]], base, bg=bg, poses=[(R, t)])
         vals.append(v)
         sigs.append(s)
     valid = sigs[0] == sigs[1] == sigs[2]

@@ -14,7 +14,8 @@ Gaussian g this module computes, in float64 from the float32 parameters:
 * 2D covariance Sigma' = J R_v Sigma R_v^T J^T + 0.3 I (low-pass dilation)
   and its inverse, the conic (a, b, c) = (S_yy, -S_xy, S_xx) / det
 * colour = max(0, sum_k sh_k Y_k(d) + 0.5), d the unit direction from the
-  camera centre C_v = -R_v^T t_v to mu.
+  camera centre C_v = -R_v^T t_v to mu (C_v held constant under pose
+  gradients).
 
 Every operation is a differentiable torch op, so ``grad64`` differentiates the
 same code.  Parity status: pinned by closed forms (isotropic on-axis and
@@ -62,15 +63,23 @@ def camera64(cam):
     return R, t, f[0], f[1], f[2], f[3], int(cam.width), int(cam.height)
 
 
-def project_view(p64, sh_degree, cam, index=None):
+def project_view(p64, sh_degree, cam, index=None, pose=None):
     """Project (a subset ``index`` of) the Gaussians into view ``cam``.
 
     p64: dict of float64 tensors in the ABI layouts (mean [3,N], log_scale
     [3,N], quat [4,N], opacity_logit [N], sh [K,3,N]).
+    pose: optional (R [3,3], t [3]) float64 tensors used in place of the
+    camera's rotation and translation in the geometry x_c = R mu + t (R a
+    general 3x3 matrix there).  The SH viewing direction always comes from
+    the camera's own pose, a constant: the paper detaches the SH colour from
+    the camera update (Sec. 3.3, "Optimization"), so pose gradients carry
+    only the geometric path.
     Returns dict with mu2 [n,2], conic [n,3] = (a, b, c), opacity [n],
     rgb [n,3], cov2 [n,3] = (S_xx, S_xy, S_yy), depth [n].
     """
     R, t, fx, fy, cx, cy, W, H = camera64(cam)
+    if pose is not None:
+        R, t = pose
     mean = p64["mean"].T
     ls = p64["log_scale"].T
     quat = p64["quat"].T
@@ -108,7 +117,8 @@ def project_view(p64, sh_degree, cam, index=None):
 
     opacity = torch.sigmoid(opl)
 
-    centre = -(R.T @ t)
+    Rc, tc = camera64(cam)[:2]
+    centre = -(Rc.T @ tc)
     dvec = mean - centre
     d = dvec / torch.linalg.vector_norm(dvec, dim=1, keepdim=True)
     basis = sh_basis(d, sh_degree)  # [n,K]

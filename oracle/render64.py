@@ -47,8 +47,11 @@ def _f32_arrays(p64):
     return {k: v.detach().numpy().astype(np.float32) for k, v in p64.items()}
 
 
-def view_setup(scene_arrays, sh_degree, cam, p64=None, tile_size=16, index_filter=None):
-    """Spec decisions, sorted visible list and FP64 projection of one view."""
+def view_setup(scene_arrays, sh_degree, cam, p64=None, tile_size=16, index_filter=None, pose=None):
+    """Spec decisions, sorted visible list and FP64 projection of one view.
+
+    pose: optional FP64 (R, t) replacing the camera's in the projected values
+    only; the FP32 decisions stay those of the camera itself."""
     if p64 is None:
         p64 = to_params64(scene_arrays)
     a32 = _f32_arrays(p64)
@@ -58,13 +61,13 @@ def view_setup(scene_arrays, sh_degree, cam, p64=None, tile_size=16, index_filte
         vis = vis[index_filter(spec, vis)]
     order = vis[np.lexsort((vis, spec["zbits"][vis]))]
     with torch.no_grad():
-        proj = project_view(p64, sh_degree, cam, index=order) if len(order) else None
+        proj = project_view(p64, sh_degree, cam, index=order, pose=pose) if len(order) else None
     pj = {k: v.numpy() for k, v in proj.items()} if proj is not None else None
     return spec, order, pj
 
 
 def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p64=None,
-                record=False):
+                record=False, pose=None):
     """Render one view (or the pixel window (x0, x1, y0, y1), half-open).
 
     Returns dict: image [3,h,w], T [h,w], count [h,w], last [h,w] (Gaussian
@@ -79,7 +82,7 @@ def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p
         i0, i1, j0, j1 = (b[vis] for b in spec["box"])
         return (i1 >= x0) & (i0 < x1) & (j1 >= y0) & (j0 < y1)
 
-    spec, order, pj = view_setup(scene_arrays, sh_degree, cam, p64=p64, index_filter=in_window)
+    spec, order, pj = view_setup(scene_arrays, sh_degree, cam, p64=p64, index_filter=in_window, pose=pose)
     bg = np.asarray(bg, dtype=np.float64)
     C = np.zeros((3, h, w))
     T = np.ones((h, w))
