@@ -14,6 +14,9 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   cpu_baseline  the FP64 CPU oracle timed on a bounded pixel sample
   per_view      the same step issued as plain per-view launches (no batching,
                 no graph), for comparison
+  pose          the same step with each view's camera-pose gradient and its
+                rig chain (central pose per frame, relative transform per
+                camera) added, as a second captured graph
 """
 from __future__ import annotations
 
@@ -157,6 +160,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-pose", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -171,7 +175,7 @@ def main():
     import torch
 
     from paper_2512_08498_amd import FusedAdam, Rasterizer
-    from workloads import config_names, make_config, make_target
+    from workloads import RIG_LAYOUT, config_names, make_config, make_target
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -218,28 +222,34 @@ def main():
         rast.l1_loss(out["image"], target, loss, dl)
         rast.backward_adam(params, out, dl, opt)
 
-    step()
-    rast.check()
-    run = step
-    if not args.no_graph:
+    def replayable(fn):
+        fn()
+        rast.check()
+        if args.no_graph:
+            return fn
         side = torch.cuda.Stream(dev)
         side.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(side):
-            step()
+            fn()
         torch.cuda.current_stream(dev).wait_stream(side)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            step()
-        run = graph.replay
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize(dev)
+            fn()
+        return graph.replay
+
+    def timed(run, steps):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize(dev)
+        return time.perf_counter() - t0
+
+    run = replayable(step)
     log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run()
-    torch.cuda.synchronize(dev)
-    elapsed = time.perf_counter() - t0
+    elapsed = timed(run, args.steps)
     rast.check()
     it_s = args.steps / elapsed
     ms = elapsed / args.steps * 1e3
@@ -336,6 +346,52 @@ def main():
         per_view = {"it_s": 1e3 / pv_ms, "ms_per_step": pv_ms, "speedup_batched": pv_ms / ms}
         log(f"per-view plain launches: {1e3 / pv_ms:.2f} it/s")
 
+    pose = None
+    if not args.no_pose:
+        # the rig of the workload: views frame-major; central pose = the
+        # frame's camera 0, relative transforms from frame 0
+        n_fr, n_cam = RIG_LAYOUT[args.config]
+        frame = np.arange(len(cams)) // n_cam
+        camid = np.arange(len(cams)) % n_cam
+        rast.set_rig(frame, camid, n_fr, n_cam)
+        T = np.zeros((len(cams), 4, 4))
+        for v, c in enumerate(cams):
+            T[v, :3, :3] = np.asarray(c.R, np.float64).reshape(3, 3)
+            T[v, :3, 3] = np.asarray(c.t, np.float64)
+            T[v, 3, 3] = 1.0
+        central = np.stack([np.concatenate([T[f * n_cam, :3, :3].reshape(-1), T[f * n_cam, :3, 3]])
+                            for f in range(n_fr)])
+        rel = [np.linalg.inv(T[0]) @ T[k] for k in range(n_cam)]
+        relative = np.stack([np.concatenate([r[:3, :3].reshape(-1), r[:3, 3]]) for r in rel])
+        c_dev = torch.from_numpy(central.astype(np.float32)).to(dev)
+        r_dev = torch.from_numpy(relative.astype(np.float32)).to(dev)
+        camg = torch.empty(len(cams), 12, dtype=torch.float32, device=dev)
+        rig_out = rast.rig_gradients(c_dev, r_dev, camg.zero_())
+
+        def step_pose():
+            rast.forward(params, out=out, check=False)
+            rast.l1_loss(out["image"], target, loss, dl)
+            rast.backward_adam(params, out, dl, opt, cam_grads=camg)
+            rast.rig_gradients(c_dev, r_dev, camg, out=rig_out)
+
+        run_pose = replayable(step_pose)
+        pose_s = timed(run_pose, args.steps)
+        rast.check()
+        pose_ms = pose_s / args.steps * 1e3
+        rast.profile(True)
+        rast.profile_read(reset=True)
+        for _ in range(args.profile_steps):
+            step_pose()
+        st_pose = rast.profile_read(reset=True)
+        rast.profile(False)
+        pre_pose = st_pose["pre_bwd"][0] / max(st_pose["pre_bwd"][1], 1)
+        pose = {"it_s": 1e3 / pose_ms, "ms_per_step": pose_ms, "overhead_ms": pose_ms - ms,
+                "pre_bwd_ms": pre_pose, "pre_bwd_ms_without": stage_ms["pre_bwd"],
+                "rig": {"frames": n_fr, "cameras": n_cam},
+                "per_record_bytes": 48 + 48 + 4}
+        log(f"with pose gradients: {1e3 / pose_ms:.2f} it/s ({pose_ms - ms:+.3f} ms/step; per-Gaussian stage "
+            f"{pre_pose:.3f} ms vs {stage_ms['pre_bwd']:.3f} ms)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a pixel sample")
@@ -371,6 +427,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_view": per_view,
+        "pose": pose,
     }
     print(json.dumps(res), flush=True)
 

@@ -100,9 +100,17 @@ typedef struct {
 } gsr_fwd_out;
 
 /* Parameter gradients, same layouts as gsr_gaussians; every entry is written
- * (invisible Gaussians get zeros).                                           */
+ * (invisible Gaussians get zeros).
+ *  camera  optional (NULL: not computed): [n_views][12] pose gradient of
+ *          each view, dL/dR (row-major, R taken as a general 3x3 matrix) then
+ *          dL/dt of x_c = R mu + t, through the projection geometry only --
+ *          the paper updates camera parameters jointly with the Gaussians and
+ *          detaches the SH colour from that update (Sec. 3.3, "Optimization").
+ *          Summed per view in a fixed order (deterministic).  gsr_adam_step
+ *          ignores it.                                                      */
 typedef struct {
   float *mean, *log_scale, *quat, *opacity_logit, *sh;
+  float *camera;
 } gsr_grads;
 
 /* Create / destroy a context.  The context owns a few device words (status
@@ -176,8 +184,11 @@ gsr_status gsr_adam_step(gsr_ctx *ctx, const gsr_grads *params, const gsr_grads 
                          int32_t sh_degree, void *stream);
 
 /* Backward and Adam fused: the per-Gaussian backward applies the Adam update
- * directly, without writing gradients (grads may be NULL) -- same result as
- * gsr_render_backward followed by gsr_adam_step with grads zeroed first.    */
+ * directly, without writing gradients (grads_out may be NULL) -- same result
+ * as gsr_render_backward followed by gsr_adam_step with grads zeroed first.
+ * grads_out, if given, receives the gradients too: its five Gaussian
+ * pointers all set or all NULL, its camera pointer as in gsr_grads (the
+ * pose gradient for a separate camera update).                            */
 gsr_status gsr_render_backward_adam(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                                     int32_t n_views, void *workspace, size_t workspace_bytes,
                                     const gsr_fwd_out *fwd, const float *dL_dimage,
@@ -255,6 +266,37 @@ typedef struct {
  * Errors: INVALID_ARG for a tile size other than 8/16/32.                  */
 gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
 gsr_status gsr_get_tuning(gsr_ctx *ctx, gsr_tuning *t);
+
+/* Rig parameterisation of the view poses (Sec. 3.1, Eq. 3, and Sec. 3.3,
+ * "Optimization"): the cameras of the rig are rigidly linked, so view v --
+ * camera c = view_camera[v] of the rig at frame f = view_frame[v] -- has the
+ * extrinsics T_v = T_m^f T_{c->m}, the product (in the order the paper
+ * writes it) of the central camera's pose at frame f and camera c's fixed
+ * relative transform.  A pose is 12 floats: R row-major, then t, of the map
+ * x -> R x + t from world to camera coordinates (the gsr_camera R, t).
+ *
+ * gsr_rig_plan: set the rig structure (HOST arrays of n_views indices,
+ * copied; synchronises).  Errors: INVALID_ARG for an index outside
+ * [0, n_frames) / [0, n_cams) or a negative size.                          */
+gsr_status gsr_rig_plan(gsr_ctx *ctx, const int32_t *view_frame, const int32_t *view_camera, int32_t n_views,
+                        int32_t n_frames, int32_t n_cams);
+
+/* Write T_v into cams[v].R, cams[v].t for every view of the rig plan
+ * (central [n_frames][12], relative [n_cams][12]; cams a DEVICE array of
+ * gsr_camera whose intrinsics and sizes are left as they are).            */
+gsr_status gsr_rig_compose(gsr_ctx *ctx, const float *central, const float *relative, gsr_camera *cams,
+                           void *stream);
+
+/* Carry the views' pose gradients view_grads [n_views][12] (gsr_grads.camera)
+ * back through T_v = T_m^f T_{c->m}: d_central [n_frames][12] = dL/dT_m^f,
+ * d_relative [n_cams][12] = dL/dT_{c->m} (written, summed over the views in
+ * view order), and optionally (NULL: skipped) the same in the tangent of a
+ * left perturbation T <- exp(xi^) T, xi = (rho, phi) with rho the
+ * translation part: xi_central [n_frames][6], xi_relative [n_cams][6].
+ * The paper fixes no update rule for the poses; these are what one needs.  */
+gsr_status gsr_rig_gradients(gsr_ctx *ctx, const float *central, const float *relative, const float *view_grads,
+                             float *d_central, float *d_relative, float *xi_central, float *xi_relative,
+                             void *stream);
 
 /* Autotuner of the batched launch (the keyframe-window batches of Sec. 3.3
  * mix resolutions, so no one tile size suits all): times forward plus

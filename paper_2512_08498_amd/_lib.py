@@ -49,14 +49,16 @@ class FwdOut(C.Structure):
 
 
 class Grads(C.Structure):
+    _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("opacity_logit", P), ("sh", P), ("camera", P)]
+
+
+class Moments(C.Structure):
     _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("opacity_logit", P), ("sh", P)]
 
 
 class AdamConfig(C.Structure):
     _fields_ = [("lr", C.c_float * 6), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
-
-Moments = Grads
 
 _SIGS = {
     "gsr_create": [C.POINTER(P)],
@@ -83,6 +85,9 @@ _SIGS = {
     "gsr_profile": [P, C.c_int32],
     "gsr_profile_read": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "gsr_last_error": [P],
+    "gsr_rig_plan": [P, P, P, C.c_int32, C.c_int32, C.c_int32],
+    "gsr_rig_compose": [P, P, P, P, P],
+    "gsr_rig_gradients": [P, P, P, P, P, P, P, P, P],
 }
 
 EXPORTED = tuple(_SIGS)

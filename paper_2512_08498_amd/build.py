@@ -26,6 +26,7 @@ SOURCES = [
     "raster_bwd.hip",
     "backward.hip",
     "misc.hip",
+    "pose.hip",
     "runtime.cpp",
     "autotune.cpp",
 ]

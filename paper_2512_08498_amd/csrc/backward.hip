@@ -10,7 +10,10 @@
 //   mean offset -> 2D mean -> x_c = R_view mu + t
 //   colour = max(0, sum sh Y(d) + 0.5) -> SH coefficients and d -> mu
 //   opacity = sigmoid(theta)
-// and, once over all views, the quaternion normalisation.
+// and, once over all views, the quaternion normalisation.  With CAM each
+// record also leaves its view's pose gradient through the geometry (T = J R
+// and x_c = R mu + t; the SH direction is detached from the pose) in cam_rec,
+// 12 floats per record, for the per-view sums of pose.hip.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -60,9 +63,13 @@ struct GroupN {
   static constexpr int N = NN;
 };
 
-template <int DEG, bool ADAM>
-__global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__restrict__ cams, Ws ws, Sizes sz,
-                                                  MutPtrs grads, int accumulate, AdamArgs adam) {
+// Three waves per SIMD: the CAM variant's extra live values would otherwise
+// push the degree-3 kernel past 168 registers and down to one or two waves,
+// which costs more than the few spills that keep it at three.
+template <int DEG, bool ADAM, bool CAM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pre_bwd(
+    GaussPtrs gp, const Cam *__restrict__ cams, Ws ws, Sizes sz, MutPtrs grads, int accumulate, AdamArgs adam,
+    float4 *__restrict__ cam_rec) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   if (ws.scalars[kOverflow]) return;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,6 +178,17 @@ __global__ __launch_bounds__(256) void k_pre_bwd(GaussPtrs gp, const Cam *__rest
     d_mean[0] += R[0] * dxc + R[3] * dyc + R[6] * dzc;
     d_mean[1] += R[1] * dxc + R[4] * dyc + R[7] * dzc;
     d_mean[2] += R[2] * dxc + R[5] * dyc + R[8] * dzc;
+    if (CAM) {
+      // dL/dR_view: rows of T = J R (row 0 = j00 R_0 + j02 R_2, row 1 =
+      // j11 R_1 + j12 R_2) plus x_c = R mu + t; dL/dt = dL/dx_c
+      float4 *o = cam_rec + (size_t)r * 3;
+      o[0] = make_float4(P.j00 * dT0[0] + dxc * m3[0], P.j00 * dT0[1] + dxc * m3[1], P.j00 * dT0[2] + dxc * m3[2],
+                         P.j11 * dT1[0] + dyc * m3[0]);
+      o[1] = make_float4(P.j11 * dT1[1] + dyc * m3[1], P.j11 * dT1[2] + dyc * m3[2],
+                         (P.j02 * dT0[0] + P.j12 * dT1[0]) + dzc * m3[0],
+                         (P.j02 * dT0[1] + P.j12 * dT1[1]) + dzc * m3[1]);
+      o[2] = make_float4((P.j02 * dT0[2] + P.j12 * dT1[2]) + dzc * m3[2], dxc, dyc, dzc);
+    }
   }
 
   // view-independent parts: scales, quaternion, opacity
@@ -318,17 +336,23 @@ __global__ __launch_bounds__(256) void k_adam(AdamSegs segs, float b1, float b2,
 }
 
 void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
-                    const MutPtrs *grads, int accumulate, const AdamArgs *adam, hipStream_t st) {
+                    const MutPtrs *grads, int accumulate, const AdamArgs *adam, float4 *cam_rec, hipStream_t st) {
   if (sz.n == 0) return;
   const unsigned blocks = (unsigned)((sz.n + 255) / 256);
   MutPtrs gr = grads ? *grads : MutPtrs{nullptr, nullptr, nullptr, nullptr, nullptr};
   AdamArgs a{};
   if (adam) a = *adam;
-#define GSR_PRE_BWD(D)                                                                     \
-  if (adam)                                                                                \
-    k_pre_bwd<D, true><<<blocks, 256, 0, st>>>(gp, cams, ws, sz, gr, accumulate, a);       \
-  else                                                                                     \
-    k_pre_bwd<D, false><<<blocks, 256, 0, st>>>(gp, cams, ws, sz, gr, accumulate, a);
+#define GSR_PRE_BWD_C(D, A)                                                                        \
+  if (cam_rec)                                                                                     \
+    k_pre_bwd<D, A, true><<<blocks, 256, 0, st>>>(gp, cams, ws, sz, gr, accumulate, a, cam_rec);   \
+  else                                                                                             \
+    k_pre_bwd<D, A, false><<<blocks, 256, 0, st>>>(gp, cams, ws, sz, gr, accumulate, a, nullptr);
+#define GSR_PRE_BWD(D)      \
+  if (adam) {               \
+    GSR_PRE_BWD_C(D, true)  \
+  } else {                  \
+    GSR_PRE_BWD_C(D, false) \
+  }
   switch (sh_degree) {
     case 0: GSR_PRE_BWD(0) break;
     case 1: GSR_PRE_BWD(1) break;
@@ -336,6 +360,7 @@ void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Si
     default: GSR_PRE_BWD(3) break;
   }
 #undef GSR_PRE_BWD
+#undef GSR_PRE_BWD_C
 }
 
 void launch_step_inc(int32_t *step, hipStream_t st) { k_step_inc<<<1, 64, 0, st>>>(step); }

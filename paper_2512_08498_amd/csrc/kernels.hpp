@@ -14,6 +14,13 @@ struct MutPtrs {
   float *mean, *log_scale, *quat, *opacity_logit, *sh;
 };
 
+// Rig structure: view v is camera cam[v] of the rig at frame frame[v]
+// (DEVICE arrays, validated on the host).
+struct RigIdx {
+  const int32_t *frame, *cam;
+  int32_t n_views, n_frames, n_cams;
+};
+
 struct AdamArgs {
   MutPtrs p, m, v;
   float lr[6];
@@ -33,7 +40,13 @@ void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, con
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);
 void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
-                    const MutPtrs *grads, int accumulate, const AdamArgs *adam, hipStream_t st);
+                    const MutPtrs *grads, int accumulate, const AdamArgs *adam, float4 *cam_rec, hipStream_t st);
+uint32_t cam_chunks(uint32_t cap_rec);
+void launch_cam_grads(const Ws &ws, const Sizes &sz, const float4 *cam_rec, float *cam_part, float *out,
+                      int accumulate, hipStream_t st);
+void launch_rig_compose(const float *central, const float *relative, const RigIdx &ri, Cam *cams, hipStream_t st);
+void launch_rig_grads(const float *central, const float *relative, const float *view_grads, const RigIdx &ri,
+                      float *d_central, float *d_relative, float *xi_central, float *xi_relative, hipStream_t st);
 void launch_adam(const MutPtrs &grads, const AdamArgs &a, int64_t n, int sh_degree, hipStream_t st);
 void launch_step_inc(int32_t *step, hipStream_t st);
 void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,

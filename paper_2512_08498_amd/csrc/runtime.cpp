@@ -20,7 +20,7 @@ namespace {
 struct Layout {
   size_t scalars, tile_count, tile_start, zero_end;
   size_t block_sums, vis_mask, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
-  size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d;
+  size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d, cam_part;
   size_t total;
 };
 
@@ -40,6 +40,9 @@ struct gsr_ctx {
   Sizes sz{};
   Layout lay{};
   float *loss_partials = nullptr;
+  // rig structure (gsr_rig_plan): frame and camera of each view, on the device
+  int32_t *rig_idx_d = nullptr;
+  int32_t rig_views = 0, rig_frames = 0, rig_cams = 0;
   // tuning applied at the next gsr_plan
   int32_t tuned_ts = 16;
   uint32_t long_list = 1024;
@@ -150,8 +153,10 @@ Layout make_layout(const Sizes &s) {
   put(L.scan_part, (scan_words + 4095) / 4096 * 4);
   put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
   put(L.tile_recs, (size_t)s.cap_pairs * 4);
-  put(L.partials, (size_t)s.cap_pairs * 48);
+  // per-pair partials; the pose gradients reuse them per record afterwards
+  put(L.partials, (size_t)std::max(s.cap_pairs, s.cap_rec) * 48);
   put(L.g2d, (size_t)s.cap_rec * 48);
+  put(L.cam_part, (size_t)cam_chunks(s.cap_rec) * (size_t)s.n_views * 48);
   L.total = o;
   return L;
 }
@@ -193,6 +198,12 @@ MutPtrs mut_ptrs(const gsr_adam_moments *g) {
 
 bool any_null(const MutPtrs &p) { return !p.mean || !p.log_scale || !p.quat || !p.opacity_logit || !p.sh; }
 
+float *cam_part(const gsr_ctx *c, void *base) { return reinterpret_cast<float *>(static_cast<char *>(base) + c->lay.cam_part); }
+
+RigIdx rig_idx(const gsr_ctx *c) {
+  return RigIdx{c->rig_idx_d, c->rig_idx_d + c->rig_views, c->rig_views, c->rig_frames, c->rig_cams};
+}
+
 }  // namespace
 
 extern "C" {
@@ -215,6 +226,7 @@ void gsr_destroy(gsr_ctx *c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->loss_partials) (void)hipFree(c->loss_partials);
+  if (c->rig_idx_d) (void)hipFree(c->rig_idx_d);
   delete c;
 }
 
@@ -351,6 +363,7 @@ gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_cam
   if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient pointer is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
+  float4 *cam_rec = grads->camera ? ws.partials : nullptr;
   {
     StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
     launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
@@ -362,7 +375,8 @@ gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_cam
   {
     StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
     launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr,
-                   accumulate ? 1 : 0, nullptr, s);
+                   accumulate ? 1 : 0, nullptr, cam_rec, s);
+    if (cam_rec) launch_cam_grads(ws, c->sz, cam_rec, cam_part(c, ws_base), grads->camera, accumulate ? 1 : 0, s);
   }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
@@ -423,10 +437,13 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   MutPtrs gr{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (grads_out) {
     gr = mut_ptrs(grads_out);
-    if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient output pointer is NULL");
+    const bool none = !gr.mean && !gr.log_scale && !gr.quat && !gr.opacity_logit && !gr.sh;
+    if (c->n > 0 && any_null(gr) && !none)
+      return fail(c, GSR_ERR_INVALID_ARG, "the Gaussian gradient outputs must be all set or all NULL");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
+  float4 *cam_rec = grads_out && grads_out->camera ? ws.partials : nullptr;
   {
     StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
     launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
@@ -438,7 +455,9 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   {
     StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
     launch_step_inc(step_dev, s);
-    launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a, s);
+    launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a,
+                   cam_rec, s);
+    if (cam_rec) launch_cam_grads(ws, c->sz, cam_rec, cam_part(c, ws_base), grads_out->camera, 0, s);
   }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
@@ -540,6 +559,59 @@ gsr_status gsr_profile_read(gsr_ctx *c, double *ms, int64_t *calls, int32_t rese
 }
 
 const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+gsr_status gsr_rig_plan(gsr_ctx *c, const int32_t *view_frame, const int32_t *view_camera, int32_t n_views,
+                        int32_t n_frames, int32_t n_cams) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (n_views < 0 || n_frames < 0 || n_cams < 0)
+    return fail(c, GSR_ERR_INVALID_ARG, "negative rig size (views %d, frames %d, cameras %d)", n_views, n_frames,
+                n_cams);
+  if (n_views > 0 && (!view_frame || !view_camera)) return fail(c, GSR_ERR_INVALID_ARG, "rig index array is NULL");
+  for (int32_t v = 0; v < n_views; ++v) {
+    if (view_frame[v] < 0 || view_frame[v] >= n_frames)
+      return fail(c, GSR_ERR_INVALID_ARG, "view %d: frame %d outside [0, %d)", v, view_frame[v], n_frames);
+    if (view_camera[v] < 0 || view_camera[v] >= n_cams)
+      return fail(c, GSR_ERR_INVALID_ARG, "view %d: camera %d outside [0, %d)", v, view_camera[v], n_cams);
+  }
+  std::vector<int32_t> idx(2 * (size_t)n_views);
+  std::copy(view_frame, view_frame + n_views, idx.begin());
+  std::copy(view_camera, view_camera + n_views, idx.begin() + n_views);
+  if (c->rig_idx_d) {
+    GSR_HIP(c, hipFree(c->rig_idx_d));
+    c->rig_idx_d = nullptr;
+  }
+  c->rig_views = c->rig_frames = c->rig_cams = 0;
+  if (n_views > 0) {
+    GSR_HIP(c, hipMalloc(&c->rig_idx_d, idx.size() * sizeof(int32_t)));
+    GSR_HIP(c, hipMemcpy(c->rig_idx_d, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  c->rig_views = n_views;
+  c->rig_frames = n_frames;
+  c->rig_cams = n_cams;
+  return GSR_OK;
+}
+
+gsr_status gsr_rig_compose(gsr_ctx *c, const float *central, const float *relative, gsr_camera *cams, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (c->rig_views > 0 && (!central || !relative || !cams))
+    return fail(c, GSR_ERR_INVALID_ARG, "a rig pose or camera pointer is NULL");
+  launch_rig_compose(central, relative, rig_idx(c), reinterpret_cast<Cam *>(cams), static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_rig_gradients(gsr_ctx *c, const float *central, const float *relative, const float *view_grads,
+                             float *d_central, float *d_relative, float *xi_central, float *xi_relative,
+                             void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if ((c->rig_frames > 0 && (!central || !d_central)) || (c->rig_cams > 0 && (!relative || !d_relative)) ||
+      (c->rig_views > 0 && !view_grads))
+    return fail(c, GSR_ERR_INVALID_ARG, "a rig pose, view gradient or output pointer is NULL");
+  launch_rig_grads(central, relative, view_grads, rig_idx(c), d_central, d_relative, xi_central, xi_relative,
+                   static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
 
 }  // extern "C"
 

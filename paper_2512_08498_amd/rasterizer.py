@@ -63,6 +63,7 @@ class Rasterizer:
         self.ctx = C.c_void_p()
         L.check(None, self.lib.gsr_create(C.byref(self.ctx)))
         self.workspace = None
+        self.rig = None
         self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(self.tile_size or 16, long_list, 0.0))))
         self._plan(capacity_records, capacity_pairs)
 
@@ -182,11 +183,24 @@ class Rasterizer:
     def check(self):
         self._check(self.lib.gsr_check(self.ctx, _vp(self.workspace), self.stream()))
 
-    def backward(self, params, fwd, dL_dimage, grads=None, accumulate=False, cams_dev=None):
+    def _cam_grad_ptr(self, cam_grads):
+        if cam_grads is None:
+            return None
+        _check_param("cam_grads", cam_grads, (self.views, 12), self.device)
+        return cam_grads.data_ptr()
+
+    def backward(self, params, fwd, dL_dimage, grads=None, accumulate=False, cams_dev=None, cam_grads=None):
+        """Gradients of every Gaussian parameter; with ``cam_grads`` (a
+        [views, 12] float32 tensor, or True for a new one) also each view's
+        pose gradient dL/d(R, t), SH detached, returned as grads["camera"]."""
         g = self._gaussians(params)
         if grads is None:
             grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
-        gr = L.Grads(*(grads[k].data_ptr() for k in PARAM_NAMES))
+        if cam_grads is True:
+            cam_grads = torch.empty(self.views, 12, dtype=torch.float32, device=self.device)
+        if cam_grads is not None:
+            grads["camera"] = cam_grads
+        gr = L.Grads(*(grads[k].data_ptr() for k in PARAM_NAMES), self._cam_grad_ptr(cam_grads))
         cams = cams_dev if cams_dev is not None else self.cams_dev
         dl = dL_dimage.contiguous()
         self._check(self.lib.gsr_render_backward(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
@@ -194,10 +208,16 @@ class Rasterizer:
                                                  C.byref(gr), 1 if accumulate else 0, self.stream()))
         return grads
 
-    def backward_adam(self, params, fwd, dL_dimage, opt: "FusedAdam", grads_out=None, cams_dev=None):
+    def backward_adam(self, params, fwd, dL_dimage, opt: "FusedAdam", grads_out=None, cams_dev=None, cam_grads=None):
+        """Backward with the Adam update fused in; ``grads_out`` (optional)
+        receives the Gaussian gradients, ``cam_grads`` (optional [views, 12])
+        the views' pose gradients."""
         g = self._gaussians(params)
         cams = cams_dev if cams_dev is not None else self.cams_dev
-        go = C.byref(L.Grads(*(grads_out[k].data_ptr() for k in PARAM_NAMES))) if grads_out is not None else None
+        go = None
+        if grads_out is not None or cam_grads is not None:
+            ptrs = [grads_out[k].data_ptr() for k in PARAM_NAMES] if grads_out is not None else [None] * 5
+            go = C.byref(L.Grads(*ptrs, self._cam_grad_ptr(cam_grads)))
         self._check(self.lib.gsr_render_backward_adam(
             self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace), self.ws_bytes,
             C.byref(self._fwd_struct(fwd)), _vp(dL_dimage), C.byref(opt.param_struct(params)),
@@ -221,6 +241,55 @@ class Rasterizer:
         calls = (C.c_int64 * L.N_STAGES)()
         self._check(self.lib.gsr_profile_read(self.ctx, ms, calls, 1 if reset else 0))
         return {name: (ms[i], calls[i]) for i, name in enumerate(L.STAGE_NAMES)}
+
+    # -- rig poses (T_v = T_m^frame T_camera->m) -------------------------------------------------
+    def set_rig(self, view_frame, view_camera, n_frames, n_cams):
+        """Rig structure of the batch: view v is camera view_camera[v] at frame view_frame[v]."""
+        vf = np.ascontiguousarray(view_frame, dtype=np.int32)
+        vc = np.ascontiguousarray(view_camera, dtype=np.int32)
+        if vf.shape != (self.views,) or vc.shape != (self.views,):
+            raise ValueError(f"rig index arrays must have {self.views} entries")
+        self._check(self.lib.gsr_rig_plan(self.ctx, vf.ctypes.data, vc.ctypes.data, self.views, int(n_frames),
+                                          int(n_cams)))
+        self.rig = (int(n_frames), int(n_cams))
+
+    def _rig_sizes(self):
+        if self.rig is None:
+            raise RuntimeError("set_rig has not been called")
+        return self.rig
+
+    def rig_compose(self, central, relative, cams_dev=None):
+        """Write the composed view poses into the camera array (default: the
+        rasterizer's own), intrinsics untouched; returns that array."""
+        F, K = self._rig_sizes()
+        _check_param("central", central, (F, 12), self.device)
+        _check_param("relative", relative, (K, 12), self.device)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self._check(self.lib.gsr_rig_compose(self.ctx, _vp(central), _vp(relative), _vp(cams), self.stream()))
+        return cams
+
+    def rig_gradients(self, central, relative, view_grads, tangent=True, out=None):
+        """dL/d(central) [F,12], dL/d(relative) [K,12] and, with ``tangent``,
+        the left-perturbation tangent gradients [F,6], [K,6] (into ``out``,
+        a dict of such tensors, if given)."""
+        F, K = self._rig_sizes()
+        _check_param("central", central, (F, 12), self.device)
+        _check_param("relative", relative, (K, 12), self.device)
+        _check_param("view_grads", view_grads, (self.views, 12), self.device)
+        if out is None:
+            f32 = dict(dtype=torch.float32, device=self.device)
+            out = dict(d_central=torch.empty(F, 12, **f32), d_relative=torch.empty(K, 12, **f32))
+            if tangent:
+                out.update(xi_central=torch.empty(F, 6, **f32), xi_relative=torch.empty(K, 6, **f32))
+        shapes = dict(d_central=(F, 12), d_relative=(K, 12), xi_central=(F, 6), xi_relative=(K, 6))
+        for k in (shapes if tangent else ("d_central", "d_relative")):
+            _check_param(k, out[k], shapes[k], self.device)
+        xc = _vp(out["xi_central"]) if tangent else None
+        xr = _vp(out["xi_relative"]) if tangent else None
+        self._check(self.lib.gsr_rig_gradients(self.ctx, _vp(central), _vp(relative), _vp(view_grads),
+                                               _vp(out["d_central"]), _vp(out["d_relative"]), xc, xr,
+                                               self.stream()))
+        return out
 
     def count_evaluations(self, out):
         """(pixel, list entry) evaluations the last forward's backward walks
@@ -261,10 +330,10 @@ class FusedAdam:
         return L.Grads(*(p[k].data_ptr() for k in PARAM_NAMES))
 
     def m_struct(self):
-        return L.Grads(*(self.m[k].data_ptr() for k in PARAM_NAMES))
+        return L.Moments(*(self.m[k].data_ptr() for k in PARAM_NAMES))
 
     def v_struct(self):
-        return L.Grads(*(self.v[k].data_ptr() for k in PARAM_NAMES))
+        return L.Moments(*(self.v[k].data_ptr() for k in PARAM_NAMES))
 
     def apply(self, grads):
         r = self.rast

@@ -51,4 +51,8 @@ def last_gaussian(rast, last_pos_v, v, vals, csr):
 
 
 def grads_to_host(grads):
-    return {k: grads[k].cpu().numpy().astype(np.float64) for k in PARAM_NAMES}
+    """Gaussian gradients, and the views' pose gradients as "cam" when present."""
+    out = {k: grads[k].cpu().numpy().astype(np.float64) for k in PARAM_NAMES}
+    if "camera" in grads:
+        out["cam"] = grads["camera"].cpu().numpy().astype(np.float64)
+    return out

@@ -70,8 +70,9 @@ def test_fullsize_window_gradients(rig):
         g[:, fwd["ambiguous"]] = 0.0
         cots[v][:, y0:y1, x0:x1] = g
     dl = torch.from_numpy(np.concatenate([c.astype(np.float32).reshape(-1) for c in cots])).cuda()
-    gpu = grads_to_host(rast.backward(params, out, dl))
-    ref = grad64(scene, cams, cots, windows=[wins.get(v) or (0, 0, 0, 0) for v in range(len(cams))])
+    gpu = grads_to_host(rast.backward(params, out, dl, cam_grads=True))
+    ref = grad64(scene, cams, cots, windows=[wins.get(v) or (0, 0, 0, 0) for v in range(len(cams))],
+                 cam_grads=True)
     for k in ref:
         scale = np.abs(ref[k]).max()
         diff = np.abs(gpu[k] - ref[k])

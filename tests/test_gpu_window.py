@@ -121,9 +121,13 @@ def test_window_gradients(window):
     dl = torch.zeros(3 * total_px, dtype=torch.float32, device="cuda")
     for v in wins:
         dl[3 * rast.pix_off[v]:3 * rast.pix_off[v + 1]] = torch.from_numpy(cots[v].reshape(-1)).cuda()
-    gpu = grads_to_host(rast.backward(params, out, dl))
+    gpu = grads_to_host(rast.backward(params, out, dl, cam_grads=True))
+    others = [v for v in range(len(cams)) if v not in wins]
+    assert not gpu["cam"][others].any()
+    gpu["cam"] = gpu["cam"][list(wins)]
     sub_cams = [cams[v] for v in wins]
-    ref = grad64(scene, sub_cams, [cots[v].astype(np.float64) for v in wins], windows=[wins[v] for v in wins])
+    ref = grad64(scene, sub_cams, [cots[v].astype(np.float64) for v in wins], windows=[wins[v] for v in wins],
+                 cam_grads=True)
     for k in ref:
         scale = np.abs(ref[k]).max()
         diff = np.abs(gpu[k] - ref[k])

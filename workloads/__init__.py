@@ -8,6 +8,7 @@ from .generators import (  # noqa: F401
     Camera,
     Scene,
     CONFIGS,
+    RIG_LAYOUT,
     make_config,
     make_target,
     config_names,

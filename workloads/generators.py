@@ -238,6 +238,10 @@ CONFIGS = {
 }
 
 
+# Rig layout of each workload's views, frame-major: (frames, cameras per frame).
+RIG_LAYOUT = {1: (1, 1), 2: (1, 1), 3: (1, 6), 4: (8, 5), 5: (4, 6)}
+
+
 def config_names():
     return {k: v[0] for k, v in CONFIGS.items()}
 
