@@ -15,8 +15,9 @@ the smoke check and the CPU baseline use it).
 * Frame sampling: frames are drawn with probability proportional to r.  The
   random numbers are inputs: pick b is the first frame f whose inclusive
   prefix sum of the weights exceeds u_b times their total.  The weights are r
-  capped at FLT_MAX / F (NaN -> 0) and summed sequentially in float32, the
-  precision the decision is taken in on both sides.
+  capped at FLT_MAX / (2F) (so that F of them cannot overflow; NaN -> 0) and
+  summed sequentially in float32, the precision the decision is taken in on
+  both sides.
 
 Parity status: X pinned by closed forms (constant image, a single pixel, a
 pure cosine), by a brute-force O(N^2) DFT on small images, and by the
@@ -66,7 +67,7 @@ def sample_frames(r, uniforms):
     """Frame index per uniform u in [0, 1), drawn proportionally to r."""
     r = np.asarray(r, np.float32)
     F = len(r)
-    cap = np.float32(np.finfo(np.float32).max / np.float32(F))
+    cap = np.float32(np.finfo(np.float32).max / np.float32(2 * F))
     w = np.where(np.isnan(r), np.float32(0.0), np.minimum(r, cap)).astype(np.float32)
     w = np.maximum(w, np.float32(0.0))
     cdf = np.zeros(F, np.float32)
