@@ -17,6 +17,9 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   pose          the same step with each view's camera-pose gradient and its
                 rig chain (central pose per frame, relative transform per
                 camera) added, as a second captured graph
+  freq          the frequency-based scheduling pass on the step's renders:
+                X of every view (batched 2D FFT) and one scheduling step,
+                timed with HIP events, with its bytes against HBM peak
 """
 from __future__ import annotations
 
@@ -161,6 +164,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-pose", action="store_true")
+    ap.add_argument("--no-freq", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -174,7 +178,7 @@ def main():
 
     import torch
 
-    from paper_2512_08498_amd import FusedAdam, Rasterizer
+    from paper_2512_08498_amd import FusedAdam, Frequency, Rasterizer
     from workloads import RIG_LAYOUT, config_names, make_config, make_target
 
     dev = torch.device("cuda", 0)
@@ -392,6 +396,34 @@ def main():
         log(f"with pose gradients: {1e3 / pose_ms:.2f} it/s ({pose_ms - ms:+.3f} ms/step; per-Gaussian stage "
             f"{pre_pose:.3f} ms vs {stage_ms['pre_bwd']:.3f} ms)")
 
+    freq = None
+    if not args.no_freq:
+        fq = Frequency(rast.sizes, device=dev)
+        x_gt = fq.significance(target)
+        x_r = torch.empty_like(x_gt)
+        levels = torch.zeros(len(cams), dtype=torch.int32, device=dev)
+        u = torch.rand(len(cams), generator=torch.Generator(device=dev).manual_seed(5), device=dev)
+        for _ in range(3):
+            fq.significance(out["image"], out=x_r)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            fq.significance(out["image"], out=x_r)
+        e1.record()
+        for _ in range(reps):
+            fq.schedule(x_gt, x_r, x_gt_level=x_gt, levels=levels, uniforms=u)
+        e2.record()
+        torch.cuda.synchronize(dev)
+        x_ms = e0.elapsed_time(e1) / reps
+        s_ms = e1.elapsed_time(e2) / reps
+        # image read once, half spectra written and read once
+        fbytes = sum(12 * w * h + 2 * 24 * (w // 2 + 1) * h for w, h in rast.sizes)
+        freq = {"significance_ms": x_ms, "schedule_ms": s_ms, "bytes": fbytes,
+                "hbm_frac": fbytes / (x_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), "images": len(cams)}
+        log(f"frequency significance of {len(cams)} views: {x_ms:.3f} ms ({freq['hbm_frac']:.1%} of HBM peak), "
+            f"schedule step {s_ms:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a pixel sample")
@@ -428,6 +460,7 @@ def main():
         "cpu_baseline": cpu,
         "per_view": per_view,
         "pose": pose,
+        "freq": freq,
     }
     print(json.dumps(res), flush=True)
 

@@ -298,6 +298,51 @@ gsr_status gsr_rig_gradients(gsr_ctx *ctx, const float *central, const float *re
                              float *d_central, float *d_relative, float *xi_central, float *xi_relative,
                              void *stream);
 
+/* Frequency-based scheduling (Sec. 3.3, "Frequency-based Scheduling",
+ * Eqs. 9-12).  The frequency significance of an RGB image is
+ *   X(I) = sum over all frequency bins (i, j) of || DFT(I)(i, j) ||_2,
+ * the unnormalised 2D DFT of each channel with the 2-norm taken over the
+ * three channels' complex values at the bin.
+ *
+ * gsr_freq_plan: fix a batch of images (HOST arrays of n_images widths and
+ * heights, copied; synchronises) and return the workspace size.  Each side
+ * must be 1..2560 with no prime factor above 7.  Errors: UNSUPPORTED for
+ * other sizes.                                                             */
+gsr_status gsr_freq_plan(gsr_ctx *ctx, const int32_t *widths, const int32_t *heights, int32_t n_images,
+                         size_t *workspace_bytes);
+
+/* X of every planned image: images holds them planar [3][h][w], one after
+ * the other in plan order (the layout of gsr_fwd_out.image); X [n_images].
+ * workspace: DEVICE, 256-byte aligned, of the planned size (the half spectra
+ * of the batch, 24 bytes per pixel and column pair).  Deterministic.      */
+gsr_status gsr_freq_significance(gsr_ctx *ctx, const float *images, void *workspace, size_t workspace_bytes,
+                                 float *X, void *stream);
+
+/* I^n of the level-of-detail structure: the mean over n x n blocks of a
+ * planar [3][height][width] image into dst [3][height/n][width/n] (rows and
+ * columns beyond a multiple of n dropped).                                */
+gsr_status gsr_downsample(gsr_ctx *ctx, const float *src, int32_t width, int32_t height, int32_t factor, float *dst,
+                          void *stream);
+
+/* One scheduling step over n_frames frames (all arrays DEVICE, float32):
+ *  r[f]  = x_gt[f] / x_render[f]            (Eq. 9; x_gt = X of the full-
+ *                                           resolution ground truth, x_render
+ *                                           = X of the current render)
+ *  r'[f] = x_gt_level[f] / x_render[f]      (Eq. 12; the ground truth at the
+ *                                           frame's current downsampling)
+ *  levels[f] -= 1 where r'[f] < tau_f and levels[f] > 0 (one level finer;
+ *                                           level 0 = full resolution)
+ *  picks[b] = the first frame whose inclusive prefix sum of the weights
+ *             exceeds uniforms[b] * (their total), the weights being r capped
+ *             at FLT_MAX / (2 n_frames), NaN taken as 0; uniform draws
+ *             floor(u n_frames) if all weights are 0.  The paper samples the
+ *             frames to optimise by r; the random numbers are the caller's.
+ * r, r_prime, levels (with x_gt_level) and picks (with uniforms) may each be
+ * NULL.  n_frames <= 16384.  The paper sets tau_f = 2 (Sec. 4).           */
+gsr_status gsr_freq_schedule(gsr_ctx *ctx, const float *x_gt, const float *x_gt_level, const float *x_render,
+                             int32_t n_frames, float tau_f, int32_t *levels, const float *uniforms, int32_t n_picks,
+                             float *r, float *r_prime, int32_t *picks, void *stream);
+
 /* Autotuner of the batched launch (the keyframe-window batches of Sec. 3.3
  * mix resolutions, so no one tile size suits all): times forward plus
  * backward on this batch for tile sizes 8, 16 and 32 and, at 16, for

@@ -86,6 +86,10 @@ _SIGS = {
     "gsr_profile_read": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "gsr_last_error": [P],
     "gsr_rig_plan": [P, P, P, C.c_int32, C.c_int32, C.c_int32],
+    "gsr_freq_plan": [P, P, P, C.c_int32, C.POINTER(C.c_size_t)],
+    "gsr_freq_significance": [P, P, P, C.c_size_t, P, P],
+    "gsr_downsample": [P, P, C.c_int32, C.c_int32, C.c_int32, P, P],
+    "gsr_freq_schedule": [P, P, P, P, C.c_int32, C.c_float, P, P, C.c_int32, P, P, P, P],
     "gsr_rig_compose": [P, P, P, P, P],
     "gsr_rig_gradients": [P, P, P, P, P, P, P, P, P],
 }

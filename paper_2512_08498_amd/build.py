@@ -27,6 +27,7 @@ SOURCES = [
     "backward.hip",
     "misc.hip",
     "pose.hip",
+    "freq.hip",
     "runtime.cpp",
     "autotune.cpp",
 ]

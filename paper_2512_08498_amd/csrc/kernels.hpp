@@ -21,6 +21,18 @@ struct RigIdx {
   int32_t n_views, n_frames, n_cams;
 };
 
+// One image of a frequency-significance batch: planar RGB [3][h][w] at float
+// offset pix_off; its half spectrum (w/2 + 1 columns of h bins per channel,
+// column-major) at float2 offset inter_off; its rows and half-spectrum
+// columns numbered from row_base and col_base across the batch.  fac_* are
+// the radices of the row (w) and column (h) transforms, tw_* the offsets of
+// their twiddle tables exp(-2 pi i t / n), t < n, in the batch's table.
+struct FreqImg {
+  int32_t w, h, nfac_w, nfac_h;
+  uint8_t fac_w[16], fac_h[16];
+  int64_t pix_off, inter_off, row_base, col_base, tw_w, tw_h;
+};
+
 struct AdamArgs {
   MutPtrs p, m, v;
   float lr[6];
@@ -42,6 +54,13 @@ void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
                     const MutPtrs *grads, int accumulate, const AdamArgs *adam, float4 *cam_rec, hipStream_t st);
 uint32_t cam_chunks(uint32_t cap_rec);
+void launch_freq_significance(const float *images, const FreqImg *imgs, int n_imgs, int64_t n_rows, int64_t n_cols,
+                              int max_w, int max_h, const float2 *tw, float2 *inter, float *col_sum, float *X,
+                              hipStream_t st);
+void launch_downsample(const float *src, int W, int H, int n, float *dst, hipStream_t st);
+void launch_freq_schedule(const float *x_gt, const float *x_gt_level, const float *x_render, int F, float tau_f,
+                          int32_t *levels, const float *u, int n_picks, float *r, float *rp, int32_t *picks,
+                          hipStream_t st);
 void launch_cam_grads(const Ws &ws, const Sizes &sz, const float4 *cam_rec, float *cam_part, float *out,
                       int accumulate, hipStream_t st);
 void launch_rig_compose(const float *central, const float *relative, const RigIdx &ri, Cam *cams, hipStream_t st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -43,6 +44,13 @@ struct gsr_ctx {
   // rig structure (gsr_rig_plan): frame and camera of each view, on the device
   int32_t *rig_idx_d = nullptr;
   int32_t rig_views = 0, rig_frames = 0, rig_cams = 0;
+  // frequency-significance batch (gsr_freq_plan)
+  std::vector<FreqImg> freq;
+  FreqImg *freq_d = nullptr;
+  float2 *freq_tw_d = nullptr;
+  int64_t freq_rows = 0, freq_cols = 0, freq_inter = 0;
+  int32_t freq_max_w = 0, freq_max_h = 0;
+  size_t freq_ws = 0;
   // tuning applied at the next gsr_plan
   int32_t tuned_ts = 16;
   uint32_t long_list = 1024;
@@ -200,6 +208,23 @@ bool any_null(const MutPtrs &p) { return !p.mean || !p.log_scale || !p.quat || !
 
 float *cam_part(const gsr_ctx *c, void *base) { return reinterpret_cast<float *>(static_cast<char *>(base) + c->lay.cam_part); }
 
+// Radices of an FFT of length n (4s first, then 2, 3, 5, 7); false if n has
+// another prime factor or needs more than 16 stages.
+bool fft_radices(int n, uint8_t *fac, int32_t &nfac) {
+  nfac = 0;
+  for (int p : {4, 2, 3, 5, 7}) {
+    while (n % p == 0) {
+      if (nfac == 16) return false;
+      fac[nfac++] = (uint8_t)p;
+      n /= p;
+    }
+  }
+  return n == 1;
+}
+
+constexpr int kFreqMaxN = 2560;      // longest row or column transform (three LDS buffers of it)
+constexpr int kFreqMaxFrames = 16384;  // frames of one scheduling step (LDS prefix sums)
+
 RigIdx rig_idx(const gsr_ctx *c) {
   return RigIdx{c->rig_idx_d, c->rig_idx_d + c->rig_views, c->rig_views, c->rig_frames, c->rig_cams};
 }
@@ -227,6 +252,8 @@ void gsr_destroy(gsr_ctx *c) {
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->loss_partials) (void)hipFree(c->loss_partials);
   if (c->rig_idx_d) (void)hipFree(c->rig_idx_d);
+  if (c->freq_d) (void)hipFree(c->freq_d);
+  if (c->freq_tw_d) (void)hipFree(c->freq_tw_d);
   delete c;
 }
 
@@ -559,6 +586,127 @@ gsr_status gsr_profile_read(gsr_ctx *c, double *ms, int64_t *calls, int32_t rese
 }
 
 const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+gsr_status gsr_freq_plan(gsr_ctx *c, const int32_t *widths, const int32_t *heights, int32_t n_images,
+                         size_t *workspace_bytes) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (n_images < 0) return fail(c, GSR_ERR_INVALID_ARG, "n_images < 0");
+  if (n_images > 0 && (!widths || !heights)) return fail(c, GSR_ERR_INVALID_ARG, "size array is NULL");
+  std::vector<FreqImg> imgs((size_t)n_images);
+  int64_t pix = 0, inter = 0, rows = 0, cols = 0;
+  int32_t max_w = 1, max_h = 1;
+  // one twiddle table exp(-2 pi i t / n) per distinct transform length,
+  // computed in double precision
+  std::vector<float2> tw;
+  std::vector<std::pair<int, int64_t>> tables;
+  auto table = [&](int n) -> int64_t {
+    for (const auto &t : tables)
+      if (t.first == n) return t.second;
+    const int64_t off = (int64_t)tw.size();
+    for (int t = 0; t < n; ++t) {
+      const double a = -2.0 * 3.14159265358979323846 * (double)t / (double)n;
+      tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+    }
+    tables.emplace_back(n, off);
+    return off;
+  };
+  for (int32_t i = 0; i < n_images; ++i) {
+    FreqImg &f = imgs[(size_t)i];
+    f = FreqImg{};
+    f.w = widths[i];
+    f.h = heights[i];
+    if (f.w < 1 || f.h < 1 || f.w > kFreqMaxN || f.h > kFreqMaxN)
+      return fail(c, GSR_ERR_UNSUPPORTED, "image %d: %d x %d outside 1..%d", i, f.w, f.h, kFreqMaxN);
+    if (!fft_radices(f.w, f.fac_w, f.nfac_w) || !fft_radices(f.h, f.fac_h, f.nfac_h))
+      return fail(c, GSR_ERR_UNSUPPORTED, "image %d: %d x %d has a prime factor above 7", i, f.w, f.h);
+    const int64_t half = f.w / 2 + 1;
+    f.pix_off = pix;
+    f.inter_off = inter;
+    f.row_base = rows;
+    f.col_base = cols;
+    f.tw_w = table(f.w);
+    f.tw_h = table(f.h);
+    pix += 3ll * f.w * f.h;
+    inter += 3 * half * f.h;
+    rows += f.h;
+    cols += half;
+    max_w = std::max(max_w, f.w);
+    max_h = std::max(max_h, f.h);
+  }
+  if (c->freq_d) {
+    GSR_HIP(c, hipFree(c->freq_d));
+    c->freq_d = nullptr;
+  }
+  if (c->freq_tw_d) {
+    GSR_HIP(c, hipFree(c->freq_tw_d));
+    c->freq_tw_d = nullptr;
+  }
+  c->freq.clear();
+  c->freq_rows = c->freq_cols = c->freq_inter = 0;
+  c->freq_ws = 0;
+  if (n_images > 0) {
+    GSR_HIP(c, hipMalloc(&c->freq_d, imgs.size() * sizeof(FreqImg)));
+    GSR_HIP(c, hipMemcpy(c->freq_d, imgs.data(), imgs.size() * sizeof(FreqImg), hipMemcpyHostToDevice));
+    GSR_HIP(c, hipMalloc(&c->freq_tw_d, tw.size() * sizeof(float2)));
+    GSR_HIP(c, hipMemcpy(c->freq_tw_d, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+  }
+  c->freq = imgs;
+  c->freq_rows = rows;
+  c->freq_cols = cols;
+  c->freq_inter = inter;
+  c->freq_max_w = max_w;
+  c->freq_max_h = max_h;
+  c->freq_ws = align_up((size_t)inter * 8) + align_up((size_t)cols * 4);
+  if (workspace_bytes) *workspace_bytes = c->freq_ws;
+  return GSR_OK;
+}
+
+gsr_status gsr_freq_significance(gsr_ctx *c, const float *images, void *ws, size_t ws_bytes, float *X, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (c->freq.empty()) return GSR_OK;
+  if (!images || !X || !ws) return fail(c, GSR_ERR_INVALID_ARG, "an image, output or workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < c->freq_ws)
+    return fail(c, GSR_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, c->freq_ws);
+  char *b = static_cast<char *>(ws);
+  float2 *inter = reinterpret_cast<float2 *>(b);
+  float *col_sum = reinterpret_cast<float *>(b + align_up((size_t)c->freq_inter * 8));
+  launch_freq_significance(images, c->freq_d, (int)c->freq.size(), c->freq_rows, c->freq_cols, c->freq_max_w,
+                           c->freq_max_h, c->freq_tw_d, inter, col_sum, X, static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_downsample(gsr_ctx *c, const float *src, int32_t width, int32_t height, int32_t factor, float *dst,
+                          void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (width < 0 || height < 0 || factor < 1)
+    return fail(c, GSR_ERR_INVALID_ARG, "bad size %d x %d or factor %d", width, height, factor);
+  if ((width / factor) * (height / factor) > 0 && (!src || !dst))
+    return fail(c, GSR_ERR_INVALID_ARG, "image pointer is NULL");
+  launch_downsample(src, width, height, factor, dst, static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_freq_schedule(gsr_ctx *c, const float *x_gt, const float *x_gt_level, const float *x_render,
+                             int32_t n_frames, float tau_f, int32_t *levels, const float *uniforms, int32_t n_picks,
+                             float *r, float *r_prime, int32_t *picks, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (n_frames < 0 || n_frames > kFreqMaxFrames || n_picks < 0)
+    return fail(c, GSR_ERR_INVALID_ARG, "n_frames %d outside 0..%d or n_picks < 0", n_frames, kFreqMaxFrames);
+  if (n_frames == 0) {
+    if (n_picks > 0) return fail(c, GSR_ERR_INVALID_ARG, "picks requested from zero frames");
+    return GSR_OK;
+  }
+  if (!x_gt || !x_render) return fail(c, GSR_ERR_INVALID_ARG, "x_gt or x_render is NULL");
+  if (levels && !x_gt_level) return fail(c, GSR_ERR_INVALID_ARG, "level updates need x_gt_level");
+  if (n_picks > 0 && (!uniforms || !picks)) return fail(c, GSR_ERR_INVALID_ARG, "uniforms or picks is NULL");
+  launch_freq_schedule(x_gt, x_gt_level, x_render, n_frames, tau_f, levels, uniforms, n_picks, r, r_prime,
+                       n_picks > 0 ? picks : nullptr, static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
 
 gsr_status gsr_rig_plan(gsr_ctx *c, const int32_t *view_frame, const int32_t *view_camera, int32_t n_views,
                         int32_t n_frames, int32_t n_cams) {
