@@ -10,6 +10,7 @@ from .generators import (  # noqa: F401
     CONFIGS,
     RIG_LAYOUT,
     make_config,
+    make_insert_inputs,
     make_target,
     config_names,
 )

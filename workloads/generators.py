@@ -238,6 +238,38 @@ CONFIGS = {
 }
 
 
+def make_insert_inputs(sizes, seed, detail_kept=0.3):
+    """Ground truth, render and z-depth per view for the insertion step:
+    the ground truth is a smooth field (a few random sinusoids) plus sharp
+    detail (random axis-aligned rectangles and single-pixel dots of random
+    colour); the render keeps the field and `detail_kept` of the detail; the
+    depth is a smooth field between 3 and 30.  Planar [3][h][w] float32 per
+    view, depth [h][w]."""
+    rng = np.random.default_rng(seed)
+    gts, rds, depths = [], [], []
+    for w, h in sizes:
+        y, x = np.mgrid[0:h, 0:w].astype(np.float64)
+        base = np.zeros((3, h, w))
+        for _ in range(4):
+            fx, fy = rng.uniform(0.5, 4.0, 2) * 2 * np.pi / np.array([w, h])
+            ph = rng.uniform(0, 2 * np.pi)
+            base += rng.uniform(0.02, 0.1, (3, 1, 1)) * np.sin(fx * x + fy * y + ph)[None]
+        base += 0.5
+        detail = np.zeros((3, h, w))
+        for _ in range(max(1, w * h // 4000)):
+            x0, y0 = int(rng.integers(0, w)), int(rng.integers(0, h))
+            x1, y1 = min(w, x0 + int(rng.integers(2, 40))), min(h, y0 + int(rng.integers(2, 40)))
+            detail[:, y0:y1, x0:x1] = rng.uniform(-0.8, 0.8, (3, 1, 1))
+        n_dots = max(1, w * h // 200)
+        detail[:, rng.integers(0, h, n_dots), rng.integers(0, w, n_dots)] += rng.uniform(-1.5, 1.5, (3, n_dots))
+        gts.append(_f32(base + detail))
+        rds.append(_f32(base + detail_kept * detail))
+        dz = 16.5 + 13.5 * np.sin(2 * np.pi * x / max(w, 2) * rng.uniform(0.2, 1.0)) * np.cos(
+            2 * np.pi * y / max(h, 2) * rng.uniform(0.2, 1.0))
+        depths.append(_f32(dz))
+    return gts, rds, depths
+
+
 # Rig layout of each workload's views, frame-major: (frames, cameras per frame).
 RIG_LAYOUT = {1: (1, 1), 2: (1, 1), 3: (1, 6), 4: (8, 5), 5: (4, 6)}
 
