@@ -20,6 +20,11 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   freq          the frequency-based scheduling pass on the step's renders:
                 X of every view (batched 2D FFT) and one scheduling step,
                 timed with HIP events, with its bytes against HBM peak
+  insert        the LoG-based insertion step over all views (seeded
+                structured ground truth, render and depth of the views'
+                sizes), timed with HIP events, bytes against HBM peak
+  merge         the per-camera merge of the scene's Gaussians with view 0's
+                samples from that insertion, timed with HIP events
 """
 from __future__ import annotations
 
@@ -165,6 +170,7 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-pose", action="store_true")
     ap.add_argument("--no-freq", action="store_true")
+    ap.add_argument("--no-insert", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -179,7 +185,7 @@ def main():
     import torch
 
     from paper_2512_08498_amd import FusedAdam, Frequency, Rasterizer
-    from workloads import RIG_LAYOUT, config_names, make_config, make_target
+    from workloads import RIG_LAYOUT, config_names, make_config, make_insert_inputs, make_target
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -424,6 +430,45 @@ def main():
         log(f"frequency significance of {len(cams)} views: {x_ms:.3f} ms ({freq['hbm_frac']:.1%} of HBM peak), "
             f"schedule step {s_ms:.3f} ms")
 
+    ins = None
+    if not args.no_insert:
+        gts, rds, depths = make_insert_inputs(rast.sizes, 7000 + args.config)
+        flat = lambda arrs: torch.from_numpy(np.concatenate([a.reshape(-1) for a in arrs])).to(dev)  # noqa: E731
+        g_d, r_d, z_d = flat(gts), flat(rds), flat(depths)
+        del gts, rds, depths
+        res = rast.log_insert(g_d, r_d, z_d)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 20
+        ev[0].record()
+        for _ in range(reps):
+            res = rast.log_insert(g_d, r_d, z_d)
+        ev[1].record()
+        torch.cuda.synchronize(dev)
+        i_ms = ev[0].elapsed_time(ev[1]) / reps
+        n_ins = int(res["count"].item())
+        # both images read, P(I) and the mask written, the mask read twice;
+        # per inserted pixel P(I) and z read, index, scale and centre written
+        ibytes = total_px * (12 + 12 + 4 + 1 + 2) + n_ins * (8 + 20)
+        ins = {"ms": i_ms, "bytes": ibytes, "hbm_frac": ibytes / (i_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+               "inserted": n_ins, "pixels": total_px}
+        log(f"LoG insertion over {len(cams)} views: {i_ms:.3f} ms ({ins['hbm_frac']:.1%} of HBM peak), "
+            f"{n_ins} pixels insert")
+        mres = rast.merge(params, 0, g_d, res, tau_d=50.0)
+        ev[0].record()
+        for _ in range(reps):
+            mres = rast.merge(params, 0, g_d, res, tau_d=50.0)
+        ev[1].record()
+        torch.cuda.synchronize(dev)
+        m_ms = ev[0].elapsed_time(ev[1]) / reps
+        w0, h0 = rast.sizes[0]
+        # per Gaussian: mean, log-scale, DC colour read twice, match written and
+        # read, keep and colour written; per pixel of the view: the slot map
+        mbytes = scene.n * (2 * 36 + 8 + 1 + 12) + w0 * h0 * 4
+        ins["merge"] = {"ms": m_ms, "bytes": mbytes, "hbm_frac": mbytes / (m_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "removed": int((mres["keep"][:scene.n] == 0).sum().item())}
+        log(f"merge of {scene.n} Gaussians with view 0's samples: {m_ms:.3f} ms "
+            f"({ins['merge']['hbm_frac']:.1%} of HBM peak)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a pixel sample")
@@ -461,6 +506,7 @@ def main():
         "per_view": per_view,
         "pose": pose,
         "freq": freq,
+        "insert": ins,
     }
     print(json.dumps(res), flush=True)
 

@@ -343,6 +343,79 @@ gsr_status gsr_freq_schedule(gsr_ctx *ctx, const float *x_gt, const float *x_gt_
                              int32_t n_frames, float tau_f, int32_t *levels, const float *uniforms, int32_t n_picks,
                              float *r, float *r_prime, int32_t *picks, void *stream);
 
+/* LoG-based insertion of new Gaussians (Sec. 3.2, "Redundancy-free Gaussian
+ * Sampling", Eqs. 4-6), over all planned views:
+ *   P(I)  = min(|| LoG_sigma * I ||_2, 1) per pixel, the norm over the three
+ *           channels' responses; LoG_sigma sampled at offsets -R..R,
+ *           R = ceil(3 sigma), as h x g + g x h with g the Gaussian (sum 1)
+ *           and h its second derivative (sum 0, second moment 2); image
+ *           borders replicated.
+ *   P_a   = max(P(I) - P(I~), 0); a pixel inserts a Gaussian when P_a > tau_a.
+ *   S     = d / (2 sqrt(P(I)) fx), d = |x_c| for the pixel centre back-
+ *           projected to the depth map's z: x_c = z ((u + 0.5 - cx) / fx,
+ *           (v + 0.5 - cy) / fy, 1); centre x_w = R^T (x_c - t).
+ * gt, render: flat planar images of all views (the gsr_fwd_out.image
+ * layout); depth: [total_pixels] z-depth; p_gt [total_pixels] receives P(I),
+ * p_render (optional) P(I~).  The inserting pixels are listed in ascending
+ * flat pixel index: out->pix, out->scale, out->mean [capacity][3]; *count
+ * (DEVICE) receives their number, which may exceed capacity (then only the
+ * first capacity are written).  workspace: DEVICE, 256-byte aligned, of
+ * gsr_insert_workspace bytes (about one byte per pixel).  The paper sets
+ * tau_a = 0.2 (Sec. 4) and leaves sigma open (0 < sigma <= 5/3 here, so
+ * R <= 5 and a tile with its halo fits the 64 KB of LDS of a workgroup).  */
+typedef struct {
+  float sigma;
+  float tau_a;
+} gsr_insert_config;
+
+typedef struct {
+  uint32_t *pix;
+  float *scale;
+  float *mean;
+  uint32_t *count;
+  int64_t capacity;
+} gsr_insert_out;
+
+gsr_status gsr_insert_workspace(gsr_ctx *ctx, size_t *bytes);
+gsr_status gsr_log_insert(gsr_ctx *ctx, const gsr_camera *cams, const float *gt, const float *render,
+                          const float *depth, const gsr_insert_config *cfg, float *p_gt, float *p_render,
+                          const gsr_insert_out *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Per-camera merging (Sec. 3.2, Eqs. 7-8): before the samples of camera i
+ * (gsr_log_insert's list; only those in view `view` are used) are added,
+ * each existing Gaussian g (mean, log_scale and the degree-0 SH of `g`)
+ * corresponds to the sample whose pixel contains its projection into the
+ * view, if z > 0.2 and | |x_c| - d | <= tau_d (d the sample centre's
+ * distance).  In each group of a sample and its corresponding Gaussians only
+ * the smallest image-space scale survives -- s' = kappa S fx / |x_c| for a
+ * Gaussian (S = exp of the mean log-scale; the paper prints kappa = 2, which
+ * disagrees with Eqs. 6 and 8 by that factor), s = 1 / (2 sqrt(P(I))) for the
+ * sample (p_gt from gsr_log_insert) -- existing Gaussians winning ties, the
+ * lower index first, and the survivor takes the group's mean colour (the
+ * Gaussians' DC colour Y0 sh_0 + 1/2, the sample's ground-truth pixel gt).
+ * Outputs: keep [n] and colour [3][n] (RGB, planar) for the Gaussians,
+ * keep_new and colour_new [capacity][3] for the view's samples (entries of
+ * other views untouched).  Deterministic (integer atomics only).
+ * workspace: DEVICE, 256-byte aligned, gsr_merge_workspace(n) bytes (40
+ * bytes per pixel of the largest view plus 4 per Gaussian).  The paper
+ * leaves tau_d open, and the re-alignment of depths unspecified (not done). */
+typedef struct {
+  float tau_d;
+  float kappa;
+} gsr_merge_config;
+
+typedef struct {
+  uint8_t *keep;
+  float *colour;
+  uint8_t *keep_new;
+  float *colour_new;
+} gsr_merge_out;
+
+gsr_status gsr_merge_workspace(gsr_ctx *ctx, int64_t n, size_t *bytes);
+gsr_status gsr_merge(gsr_ctx *ctx, const gsr_gaussians *g, int32_t view, const gsr_camera *cams, const float *gt,
+                     const float *p_gt, const gsr_insert_out *samples, const gsr_merge_config *cfg,
+                     const gsr_merge_out *out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Autotuner of the batched launch (the keyframe-window batches of Sec. 3.3
  * mix resolutions, so no one tile size suits all): times forward plus
  * backward on this batch for tile sizes 8, 16 and 32 and, at 16, for

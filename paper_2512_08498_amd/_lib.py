@@ -52,6 +52,22 @@ class Grads(C.Structure):
     _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("opacity_logit", P), ("sh", P), ("camera", P)]
 
 
+class InsertConfig(C.Structure):
+    _fields_ = [("sigma", C.c_float), ("tau_a", C.c_float)]
+
+
+class InsertOut(C.Structure):
+    _fields_ = [("pix", P), ("scale", P), ("mean", P), ("count", P), ("capacity", C.c_int64)]
+
+
+class MergeConfig(C.Structure):
+    _fields_ = [("tau_d", C.c_float), ("kappa", C.c_float)]
+
+
+class MergeOut(C.Structure):
+    _fields_ = [("keep", P), ("colour", P), ("keep_new", P), ("colour_new", P)]
+
+
 class Moments(C.Structure):
     _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("opacity_logit", P), ("sh", P)]
 
@@ -87,6 +103,11 @@ _SIGS = {
     "gsr_last_error": [P],
     "gsr_rig_plan": [P, P, P, C.c_int32, C.c_int32, C.c_int32],
     "gsr_freq_plan": [P, P, P, C.c_int32, C.POINTER(C.c_size_t)],
+    "gsr_insert_workspace": [P, C.POINTER(C.c_size_t)],
+    "gsr_merge_workspace": [P, C.c_int64, C.POINTER(C.c_size_t)],
+    "gsr_merge": [P, C.POINTER(Gaussians), C.c_int32, P, P, P, C.POINTER(InsertOut), C.POINTER(MergeConfig),
+                  C.POINTER(MergeOut), P, C.c_size_t, P],
+    "gsr_log_insert": [P, P, P, P, P, C.POINTER(InsertConfig), P, P, C.POINTER(InsertOut), P, C.c_size_t, P],
     "gsr_freq_significance": [P, P, P, C.c_size_t, P, P],
     "gsr_downsample": [P, P, C.c_int32, C.c_int32, C.c_int32, P, P],
     "gsr_freq_schedule": [P, P, P, P, C.c_int32, C.c_float, P, P, C.c_int32, P, P, P, P],

@@ -28,6 +28,8 @@ SOURCES = [
     "misc.hip",
     "pose.hip",
     "freq.hip",
+    "insert.hip",
+    "merge.hip",
     "runtime.cpp",
     "autotune.cpp",
 ]

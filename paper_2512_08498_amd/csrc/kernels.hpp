@@ -33,6 +33,13 @@ struct FreqImg {
   int64_t pix_off, inter_off, row_base, col_base, tw_w, tw_h;
 };
 
+// Taps of the sampled LoG: g (Gaussian, sum 1) and h (second derivative,
+// sum 0, second moment 2) at offsets -R..R, R <= 5 (room for R <= 8).
+struct LogTaps {
+  float g[17], h[17];
+  int32_t R;
+};
+
 struct AdamArgs {
   MutPtrs p, m, v;
   float lr[6];
@@ -57,6 +64,19 @@ uint32_t cam_chunks(uint32_t cap_rec);
 void launch_freq_significance(const float *images, const FreqImg *imgs, int n_imgs, int64_t n_rows, int64_t n_cols,
                               int max_w, int max_h, const float2 *tw, float2 *inter, float *col_sum, float *X,
                               hipStream_t st);
+uint32_t ins_tiles(const ViewInfo *views_host, int n_views);
+uint32_t ins_blocks(int64_t n_pix);
+size_t ins_lds_bytes(int R);
+void launch_log_insert(const ViewInfo *views_d, int n_views, uint32_t n_tiles, int64_t n_pix, const Cam *cams,
+                       const float *gt, const float *rd, const float *depth, const LogTaps &taps, float tau,
+                       float *p_gt, float *p_rd, uint8_t *mask, uint32_t *counts, uint32_t *offsets,
+                       uint32_t *total, uint32_t *out_pix, float *out_scale, float *out_mean, int64_t capacity,
+                       hipStream_t st);
+void launch_merge(const GaussPtrs &gp, int64_t n, const Cam *cams, int view, const ViewInfo &vi, const float *gt,
+                  const float *p_gt, const uint32_t *pix, const float *s_mean, const uint32_t *count,
+                  int64_t capacity, float tau_d, float kappa, int32_t *slot, uint32_t *cnt, unsigned long long *csum,
+                  unsigned long long *win, int32_t *match, uint8_t *keep, float *colour, uint8_t *keep_new,
+                  float *colour_new, hipStream_t st);
 void launch_downsample(const float *src, int W, int H, int n, float *dst, hipStream_t st);
 void launch_freq_schedule(const float *x_gt, const float *x_gt_level, const float *x_render, int F, float tau_f,
                           int32_t *levels, const float *u, int n_picks, float *r, float *rp, int32_t *picks,

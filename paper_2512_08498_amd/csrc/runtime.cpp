@@ -708,6 +708,140 @@ gsr_status gsr_freq_schedule(gsr_ctx *c, const float *x_gt, const float *x_gt_le
   return GSR_OK;
 }
 
+// Workspace of gsr_log_insert: the byte mask, then the per-block counts and
+// offsets of the compaction, then the total.
+struct InsLayout {
+  size_t mask, counts, offsets, total, bytes;
+};
+
+InsLayout ins_layout(const gsr_ctx *c) {
+  InsLayout L{};
+  const int64_t px = c->views.empty() ? 0 : (int64_t)c->views.back().pix_off + (int64_t)c->views.back().w * c->views.back().h;
+  const size_t nb = ins_blocks(px);
+  L.mask = 0;
+  L.counts = align_up((size_t)px);
+  L.offsets = L.counts + align_up(nb * 4);
+  L.total = L.offsets + align_up(nb * 4);
+  L.bytes = L.total + 256;
+  return L;
+}
+
+gsr_status gsr_insert_workspace(gsr_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  *bytes = ins_layout(c).bytes;
+  return GSR_OK;
+}
+
+gsr_status gsr_log_insert(gsr_ctx *c, const gsr_camera *cams, const float *gt, const float *render, const float *depth,
+                          const gsr_insert_config *cfg, float *p_gt, float *p_render, const gsr_insert_out *out,
+                          void *ws, size_t ws_bytes, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (!cams || !gt || !render || !depth || !cfg || !p_gt || !out || !ws)
+    return fail(c, GSR_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (!(cfg->sigma > 0.0f && cfg->sigma <= 5.0f / 3.0f))
+    return fail(c, GSR_ERR_INVALID_ARG, "sigma %g outside (0, 5/3]", (double)cfg->sigma);
+  if (out->capacity < 0 || !out->count || (out->capacity > 0 && (!out->pix || !out->scale || !out->mean)))
+    return fail(c, GSR_ERR_INVALID_ARG, "insertion output arrays missing");
+  const InsLayout L = ins_layout(c);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.bytes) return fail(c, GSR_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
+  // taps in double precision, rounded once
+  LogTaps taps{};
+  const double sg = cfg->sigma;
+  const int R = (int)std::ceil(3.0 * sg);
+  double g[17], h[17], gs = 0.0, hs = 0.0, hm = 0.0;
+  for (int k = 0; k <= 2 * R; ++k) {
+    const double x = k - R;
+    g[k] = std::exp(-x * x / (2.0 * sg * sg));
+    gs += g[k];
+  }
+  for (int k = 0; k <= 2 * R; ++k) {
+    const double x = k - R;
+    g[k] /= gs;
+    h[k] = (x * x - sg * sg) / (sg * sg * sg * sg) * g[k];
+    hs += h[k];
+  }
+  for (int k = 0; k <= 2 * R; ++k) {
+    const double x = k - R;
+    h[k] -= hs / (2 * R + 1);
+    hm += x * x * h[k];
+  }
+  for (int k = 0; k <= 2 * R; ++k) {
+    taps.g[k] = (float)g[k];
+    taps.h[k] = (float)(h[k] * 2.0 / hm);
+  }
+  taps.R = R;
+  const int64_t px = (int64_t)c->views.back().pix_off + (int64_t)c->views.back().w * c->views.back().h;
+  char *b = static_cast<char *>(ws);
+  launch_log_insert(c->views_d, c->n_views, ins_tiles(c->views.data(), c->n_views), px,
+                    reinterpret_cast<const Cam *>(cams), gt, render, depth, taps, cfg->tau_a, p_gt, p_render,
+                    reinterpret_cast<uint8_t *>(b + L.mask), reinterpret_cast<uint32_t *>(b + L.counts),
+                    reinterpret_cast<uint32_t *>(b + L.offsets), out->count, out->pix, out->scale, out->mean,
+                    out->capacity, static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+// Workspace of gsr_merge: per pixel of the largest view the slot, the group
+// count, colour sums (3 x 64 bit) and the 64-bit winner key; per Gaussian the
+// matched pixel.
+struct MergeLayout {
+  size_t slot, cnt, csum, win, match, bytes;
+};
+
+MergeLayout merge_layout(const gsr_ctx *c, int64_t n) {
+  MergeLayout L{};
+  size_t px = 0;
+  for (const ViewInfo &v : c->views) px = std::max(px, (size_t)v.w * (size_t)v.h);
+  L.slot = 0;
+  L.cnt = align_up(px * 4);
+  L.csum = L.cnt + align_up(px * 4);
+  L.win = L.csum + align_up(px * 24);
+  L.match = L.win + align_up(px * 8);
+  L.bytes = L.match + align_up((size_t)std::max<int64_t>(n, 1) * 4);
+  return L;
+}
+
+gsr_status gsr_merge_workspace(gsr_ctx *c, int64_t n, size_t *bytes) {
+  if (!c || !bytes || n < 0) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  *bytes = merge_layout(c, n).bytes;
+  return GSR_OK;
+}
+
+gsr_status gsr_merge(gsr_ctx *c, const gsr_gaussians *g, int32_t view, const gsr_camera *cams, const float *gt,
+                     const float *p_gt, const gsr_insert_out *samples, const gsr_merge_config *cfg,
+                     const gsr_merge_out *out, void *ws, size_t ws_bytes, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (!g || !cams || !gt || !p_gt || !samples || !cfg || !out || !ws)
+    return fail(c, GSR_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (view < 0 || view >= c->n_views) return fail(c, GSR_ERR_INVALID_ARG, "view %d outside [0, %d)", view, c->n_views);
+  if (g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return fail(c, GSR_ERR_INVALID_ARG, "bad Gaussian set");
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->sh || !out->keep || !out->colour))
+    return fail(c, GSR_ERR_INVALID_ARG, "a Gaussian or output pointer is NULL");
+  if (g->n >= (int64_t)0xFFFFFFFFll) return fail(c, GSR_ERR_UNSUPPORTED, "more than 2^32 - 1 Gaussians");
+  if (samples->capacity < 0 || !samples->count ||
+      (samples->capacity > 0 && (!samples->pix || !samples->mean || !out->keep_new || !out->colour_new)))
+    return fail(c, GSR_ERR_INVALID_ARG, "sample arrays missing");
+  if (!(cfg->tau_d >= 0.0f) || !(cfg->kappa > 0.0f))
+    return fail(c, GSR_ERR_INVALID_ARG, "tau_d must be >= 0 and kappa > 0");
+  const MergeLayout L = merge_layout(c, g->n);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.bytes) return fail(c, GSR_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
+  char *b = static_cast<char *>(ws);
+  launch_merge(gauss_ptrs(g), g->n, reinterpret_cast<const Cam *>(cams), view, c->views[(size_t)view], gt, p_gt,
+               samples->pix, samples->mean, samples->count, samples->capacity, cfg->tau_d, cfg->kappa,
+               reinterpret_cast<int32_t *>(b + L.slot), reinterpret_cast<uint32_t *>(b + L.cnt),
+               reinterpret_cast<unsigned long long *>(b + L.csum), reinterpret_cast<unsigned long long *>(b + L.win),
+               reinterpret_cast<int32_t *>(b + L.match), out->keep, out->colour, out->keep_new, out->colour_new,
+               static_cast<hipStream_t>(stream));
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
 gsr_status gsr_rig_plan(gsr_ctx *c, const int32_t *view_frame, const int32_t *view_camera, int32_t n_views,
                         int32_t n_frames, int32_t n_cams) {
   if (!c) return GSR_ERR_INVALID_ARG;

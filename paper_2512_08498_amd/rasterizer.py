@@ -79,6 +79,8 @@ class Rasterizer:
         self.pix_off = [int(p) for p in pix]
         self.total_px = self.pix_off[-1]
         self.workspace = None
+        self._ins_ws = None
+        self._merge_ws = None
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
     def tuning(self):
@@ -290,6 +292,67 @@ class Rasterizer:
                                                _vp(out["d_central"]), _vp(out["d_relative"]), xc, xr,
                                                self.stream()))
         return out
+
+    # -- LoG-based insertion of new Gaussians -------------------------------------------------
+    def log_insert(self, gt, render, depth, sigma=1.0, tau_a=0.2, capacity=None, cams_dev=None, p_render=False):
+        """Insertion probabilities of all views and the list of inserting
+        pixels with the new Gaussians' scale and world centre (see
+        gsr_log_insert).  Returns dict(p_gt, p_render, pix, scale, mean, count)."""
+        px = self.total_px
+        _check_param("gt", gt, (3 * px,), self.device)
+        _check_param("render", render, (3 * px,), self.device)
+        _check_param("depth", depth, (px,), self.device)
+        if getattr(self, "_ins_ws", None) is None:
+            nb = C.c_size_t()
+            self._check(self.lib.gsr_insert_workspace(self.ctx, C.byref(nb)))
+            self._ins_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        cap = px if capacity is None else int(capacity)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        res = dict(p_gt=torch.empty(px, **f32), p_render=torch.empty(px, **f32) if p_render else None,
+                   pix=torch.empty(max(cap, 1), dtype=torch.int32, device=self.device),
+                   scale=torch.empty(max(cap, 1), **f32), mean=torch.empty(max(cap, 1), 3, **f32),
+                   count=torch.zeros(1, dtype=torch.int32, device=self.device))
+        out = L.InsertOut(res["pix"].data_ptr(), res["scale"].data_ptr(), res["mean"].data_ptr(),
+                          res["count"].data_ptr(), cap)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self._check(self.lib.gsr_log_insert(self.ctx, _vp(cams), _vp(gt), _vp(render), _vp(depth),
+                                            C.byref(L.InsertConfig(float(sigma), float(tau_a))), _vp(res["p_gt"]),
+                                            _vp(res["p_render"]) if p_render else None, C.byref(out),
+                                            _vp(self._ins_ws), self._ins_ws.numel(), self.stream()))
+        return res
+
+    def merge(self, existing, view, gt, ins, tau_d, kappa=1.0, cams_dev=None):
+        """Merge the existing Gaussians (dict with mean [3, n], log_scale
+        [3, n], sh [K, 3, n]) with the samples of ``view`` from ``ins`` (a
+        log_insert result): returns dict(keep [n] uint8, colour [3, n],
+        keep_new [capacity] uint8, colour_new [capacity, 3]) (see gsr_merge)."""
+        n = existing["mean"].shape[1]
+        k = existing["sh"].shape[0]
+        deg = int(round(k ** 0.5)) - 1
+        for name, shape in (("mean", (3, n)), ("log_scale", (3, n)), ("sh", (k, 3, n))):
+            _check_param(name, existing[name], shape, self.device)
+        _check_param("gt", gt, (3 * self.total_px,), self.device)
+        cap = ins["pix"].numel()
+        nb = C.c_size_t()
+        self._check(self.lib.gsr_merge_workspace(self.ctx, n, C.byref(nb)))
+        ws = getattr(self, "_merge_ws", None)
+        if ws is None or ws.numel() < int(nb.value):
+            ws = self._merge_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        res = dict(keep=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
+                   colour=torch.empty(3, max(n, 1), dtype=torch.float32, device=self.device),
+                   keep_new=torch.zeros(cap, dtype=torch.uint8, device=self.device),
+                   colour_new=torch.zeros(cap, 3, dtype=torch.float32, device=self.device))
+        g = L.Gaussians(n, deg, existing["mean"].data_ptr(), existing["log_scale"].data_ptr(), None, None,
+                        existing["sh"].data_ptr())
+        so = L.InsertOut(ins["pix"].data_ptr(), ins["scale"].data_ptr(), ins["mean"].data_ptr(),
+                         ins["count"].data_ptr(), cap)
+        mo = L.MergeOut(res["keep"].data_ptr(), res["colour"].data_ptr(), res["keep_new"].data_ptr(),
+                        res["colour_new"].data_ptr())
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self._check(self.lib.gsr_merge(self.ctx, C.byref(g), int(view), _vp(cams), _vp(gt), _vp(ins["p_gt"]),
+                                       C.byref(so), C.byref(L.MergeConfig(float(tau_d), float(kappa))), C.byref(mo),
+                                       _vp(ws), ws.numel(), self.stream()))
+        return res
 
     def count_evaluations(self, out):
         """(pixel, list entry) evaluations the last forward's backward walks

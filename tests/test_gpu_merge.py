@@ -1,0 +1,116 @@
+"""Per-camera merging through the C ABI against the FP64 oracle
+(oracle/merge64.py): keep flags of the existing Gaussians and of the view's
+samples bit for bit, and the surviving colours within 1e-6, on groups whose
+decisions are not within 1e-5 of a threshold; other views' samples are left
+alone; on a small posed view with placed Gaussians and on the rig's 1600x900
+views with the 1M-Gaussian scene as the existing set (the samples there are
+the oracle's own insertion lists of seeded synthetic images)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import log
+from oracle.insert64 import insert
+from oracle.merge64 import merge
+from paper_2512_08498_amd import Rasterizer
+from tiny_scenes import camera
+from workloads import make_config, make_insert_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _samples_for(rast, cams, view, pix_local, centres, gt_flat):
+    """Device sample list (global pixel indices, centres) for one view, and the host dict."""
+    off = rast.pix_off[view]
+    cap = len(pix_local) + 5
+    pix = np.zeros(cap, np.int32)
+    pix[:len(pix_local)] = (pix_local + off).astype(np.int32)
+    mean = np.zeros((cap, 3), np.float32)
+    mean[:len(pix_local)] = centres
+    w, h = rast.sizes[view]
+    img = gt_flat[3 * off:3 * (off + w * h)].reshape(3, h * w)
+    host = dict(pix=pix_local, centre=centres.astype(np.float32).astype(np.float64),
+                colour=img[:, pix_local].T.astype(np.float64))
+    dev = dict(pix=torch.from_numpy(pix).cuda(), mean=torch.from_numpy(mean).cuda(),
+               scale=torch.zeros(cap, dtype=torch.float32, device="cuda"),
+               count=torch.tensor([len(pix_local)], dtype=torch.int32, device="cuda"))
+    return host, dev
+
+
+def _compare(res, ref, n, k):
+    keep = res["keep"][:n].cpu().numpy().astype(bool)
+    colour = res["colour"][:, :n].cpu().numpy().astype(np.float64).T
+    keep_new = res["keep_new"][:k].cpu().numpy().astype(bool)
+    colour_new = res["colour_new"][:k].cpu().numpy().astype(np.float64)
+    ok_g, ok_n = ~ref["ambiguous_g"], ~ref["ambiguous_new"]
+    assert np.array_equal(keep[ok_g], ref["keep"][ok_g])
+    assert np.array_equal(keep_new[ok_n], ref["keep_new"][ok_n])
+    assert np.abs(colour[ok_g] - ref["colour"][ok_g]).max() <= 1e-6
+    assert np.abs(colour_new[ok_n] - ref["colour_new"][ok_n]).max() <= 1e-6
+    log(f"  {int((ref['match'] >= 0).sum())} matched Gaussians, {int((~ref['keep']).sum())} removed, "
+        f"{int((~ref['keep_new']).sum())} of {k} samples dropped; ambiguous {int(ref['ambiguous_g'].sum())} "
+        f"Gaussians, {int(ref['ambiguous_new'].sum())} samples")
+    return int((ref["match"] >= 0).sum())
+
+
+@pytest.mark.parametrize("kappa", [1.0, 2.0])
+def test_merge_small_view(kappa):
+    rng = np.random.default_rng(60)
+    a = 0.15
+    R = np.array([[math.cos(a), 0, math.sin(a)], [0, 1, 0], [-math.sin(a), 0, math.cos(a)]])
+    cams = [camera(f=50.0, w=40, h=30), camera(f=60.0, w=48, h=32, R=R, t=np.array([0.1, 0.0, -0.2]))]
+    rast = Rasterizer(cams, 1, 0)
+    view = 1
+    W, H = 48, 32
+    K, N = 80, 600
+    pix = np.sort(rng.choice(W * H, K, replace=False))
+    z = rng.uniform(2, 7, K)
+    u, v = pix % W + 0.5, pix // W + 0.5
+    xc = np.stack([z * (u - 24) / 60, z * (v - 16) / 60, z], 1)
+    Rf = np.asarray(cams[1].R, np.float32).astype(np.float64)
+    tf = np.asarray(cams[1].t, np.float32).astype(np.float64)
+    centres = ((xc - tf) @ Rf).astype(np.float32)
+    mean = np.stack([rng.uniform(-2, 2, N), rng.uniform(-1.5, 1.5, N), rng.uniform(-1, 8, N)])
+    for g in range(0, N, 2):
+        k = rng.integers(0, K)
+        mean[:, g] = (xc[k] * rng.uniform(0.92, 1.08) - tf) @ Rf
+    mean = mean.astype(np.float32)
+    ls = rng.normal(-3.0, 0.6, (3, N)).astype(np.float32)
+    sh = rng.normal(0, 1, (1, 3, N)).astype(np.float32)
+    gt = rng.uniform(0, 1, 3 * rast.total_px).astype(np.float32)
+    p = rng.uniform(0.05, 1.0, rast.total_px).astype(np.float32)
+    host, dev = _samples_for(rast, cams, view, pix, centres, gt)
+    dev["p_gt"] = torch.from_numpy(p).cuda()
+    ex = {k_: torch.from_numpy(np.ascontiguousarray(v_)).cuda() for k_, v_ in
+          (("mean", mean), ("log_scale", ls), ("sh", sh))}
+    res = rast.merge(ex, view, torch.from_numpy(gt).cuda(), dev, tau_d=0.4, kappa=kappa)
+    torch.cuda.synchronize()
+    p_view = p[rast.pix_off[1]:rast.pix_off[2]].reshape(H, W)
+    ref = merge(mean, ls, sh[0], cams[1], host, p_view, tau_d=0.4, kappa=kappa)
+    assert _compare(res, ref, N, K) > 50
+    # the spare entries (and any other view's) are untouched
+    assert not res["keep_new"][K:].any()
+
+
+def test_merge_rig_views_with_the_scene():
+    scene, cams = make_config(3)
+    rast = Rasterizer(cams, 1, 0)
+    gts, rds, depths = make_insert_inputs(rast.sizes, 61)
+    gt_flat = np.concatenate([g.reshape(-1) for g in gts])
+    ex = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in scene.arrays().items()}
+    sh0 = scene.sh[0]
+    total = 0
+    for view in (0, 3):
+        o = insert(gts[view], rds[view], depths[view], cams[view])
+        host, dev = _samples_for(rast, cams, view, o["pix"], o["mean"].astype(np.float32), gt_flat)
+        p_full = np.zeros(rast.total_px, np.float32)
+        p_full[rast.pix_off[view]:rast.pix_off[view + 1]] = o["p_gt"].reshape(-1)
+        dev["p_gt"] = torch.from_numpy(p_full).cuda()
+        res = rast.merge(ex, view, torch.from_numpy(gt_flat).cuda(), dev, tau_d=50.0)
+        torch.cuda.synchronize()
+        ref = merge(scene.mean, scene.log_scale, sh0, cams[view], host, o["p_gt"].astype(np.float32), tau_d=50.0)
+        log(f"view {view}: {len(o['pix'])} samples")
+        total += _compare(res, ref, scene.n, len(o["pix"]))
+    assert total > 100
