@@ -2,8 +2,9 @@
 """Training-iteration benchmark of the differentiable Gaussian rasterizer.
 
 One step = forward render of every view of the batch, L1 loss against the
-target images, backward to all Gaussian parameters and a dense Adam update
-(fused into the per-Gaussian backward), all in the HIP library, replayed as
+target images (fused into the compositing epilogue), backward to all
+Gaussian parameters and a dense Adam update (fused into the per-Gaussian
+backward), all in the HIP library, replayed as
 one captured HIP graph.  Default workload: the 6-camera 1600x900 ring rig in
 a street corridor with 1M Gaussians (SH degree 3).
 
@@ -73,10 +74,10 @@ def stage_work(stage, n, n_u, pg, views, px, rec, pairs, tiles, evals):
         return 24 * rec + 12 * pairs + 8 * pairs + 8 * tiles, 0
     if stage == "sort":         # (key, value) pairs in and out
         return 24 * pairs, 0
-    if stage == "raster_fwd":   # lists + records in; image, T, last, count out
-        return 40 * pairs + 20 * px, FWD_OPS_PER_EVAL * evals
-    if stage == "loss":         # image + target in; gradient out
-        return 36 * px, 0
+    if stage == "raster_fwd":   # lists + records in; image, T, last, count out; the fused L1 loss:
+        return 40 * pairs + 20 * px + 24 * px, FWD_OPS_PER_EVAL * evals  # target in, gradient out
+    if stage == "loss":         # the final sum of the fused loss's per-workgroup partials
+        return 4 * tiles, 0
     if stage == "raster_bwd":   # lists, records, dL/dC, T, last in
         return 40 * pairs + 20 * px, BWD_OPS_PER_EVAL * evals
     if stage == "reduce":       # per-record 2D gradients out and back in
@@ -228,8 +229,7 @@ def main():
     dl = torch.empty_like(out["image"])
 
     def step():
-        rast.forward(params, out=out, check=False)
-        rast.l1_loss(out["image"], target, loss, dl)
+        rast.forward_l1(params, target, out=out, loss_out=loss, dl_out=dl, check=False)
         rast.backward_adam(params, out, dl, opt)
 
     def replayable(fn):
@@ -379,8 +379,7 @@ def main():
         rig_out = rast.rig_gradients(c_dev, r_dev, camg.zero_())
 
         def step_pose():
-            rast.forward(params, out=out, check=False)
-            rast.l1_loss(out["image"], target, loss, dl)
+            rast.forward_l1(params, target, out=out, loss_out=loss, dl_out=dl, check=False)
             rast.backward_adam(params, out, dl, opt, cam_grads=camg)
             rast.rig_gradients(c_dev, r_dev, camg, out=rig_out)
 

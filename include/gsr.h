@@ -150,6 +150,17 @@ gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_ca
 gsr_status gsr_l1_loss(gsr_ctx *ctx, const float *image, const float *target, int64_t n_elems,
                        float *loss_out, float *dL_dimage, void *stream);
 
+/* gsr_render_forward with the L1 loss of gsr_l1_loss fused into the
+ * compositing epilogue: target (same layout as the image, all planned
+ * pixels), *loss_out (DEVICE float), dL_dimage (same layout).  dL_dimage is
+ * bit for bit that of gsr_l1_loss; the loss is summed per wave and then in a
+ * fixed order (deterministic, and equal to gsr_l1_loss up to the order of
+ * the float additions).  The image and the fwd outputs are as for
+ * gsr_render_forward.                                                       */
+gsr_status gsr_render_forward_l1(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                 void *workspace, size_t workspace_bytes, const gsr_fwd_out *out,
+                                 const float *target, float *loss_out, float *dL_dimage, void *stream);
+
 /* Reverse-order adjoint of gsr_render_forward: from dL/dimage (same layout as
  * the image) to gradients of every Gaussian parameter.  Reads the forward's
  * workspace state and the fwd outputs t_final / last_pos.  Overwrites grads

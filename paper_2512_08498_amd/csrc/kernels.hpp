@@ -40,6 +40,16 @@ struct LogTaps {
   int32_t R;
 };
 
+// L1 loss fused into the forward compositing (NULL target: none): per
+// pixel dl = sign(image - target) * inv_n and the sum of |image - target|
+// per workgroup into part[workgroup].
+struct LossArgs {
+  const float *target;
+  float *dl;
+  float *part;
+  float inv_n;
+};
+
 struct AdamArgs {
   MutPtrs p, m, v;
   float lr[6];
@@ -54,7 +64,9 @@ void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_tile_csr(const Ws &ws, const Sizes &sz, uint32_t *csr, hipStream_t st);
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
-                       uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st);
+                       uint32_t *last_pos, uint32_t *n_contrib, const LossArgs &loss, hipStream_t st);
+void launch_l1_final(const float *partials, uint32_t nb, int64_t n, float *loss, hipStream_t st);
+uint32_t raster_fwd_grid(const Sizes &sz);
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);
 void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st);

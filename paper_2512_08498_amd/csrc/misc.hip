@@ -57,6 +57,28 @@ __global__ __launch_bounds__(256) void k_l1_final(const float *__restrict__ part
   if (threadIdx.x == 0) *loss = (float)(((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)n);
 }
 
+// The mean from many partials: 1024 threads, thread t adding partials
+// t, t + 1024, ... in order (in double), then the 16 waves' sums in order.
+__global__ __launch_bounds__(1024) void k_l1_sum(const float *__restrict__ partials, uint32_t nb, int64_t n,
+                                                 float *__restrict__ loss) {
+  __shared__ double s_d[16];
+  double s = 0.0;
+#pragma unroll 4
+  for (uint32_t b = threadIdx.x; b < nb; b += 1024u) s += (double)partials[b];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane_id() == 0) s_d[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = s_d[0];
+    for (int w = 1; w < 16; ++w) t += s_d[w];
+    *loss = (float)(t / (double)n);
+  }
+}
+
+void launch_l1_final(const float *partials, uint32_t nb, int64_t n, float *loss, hipStream_t st) {
+  k_l1_sum<<<1, 1024, 0, st>>>(partials, nb, n, loss);
+}
+
 void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float *dl, float *partials,
                hipStream_t st) {
   const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |

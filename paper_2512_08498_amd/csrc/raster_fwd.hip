@@ -5,7 +5,11 @@
 // Records are staged in LDS in batches (one per thread, four float4 each,
 // stored as four arrays so all lanes read the same address: LDS broadcast).
 // Per pixel the kernel keeps T, the colour and the position one past the
-// last composited entry, which the backward pass starts from.
+// last composited entry, which the backward pass starts from.  With a
+// target image the L1 loss is fused into the epilogue: dL/dimage per pixel
+// and |image - target| summed per workgroup (a fixed butterfly per wave, then
+// the waves in order), one partial per workgroup, added up in order by
+// k_l1_sum.
 #include "kernels.hpp"
 #include "raster.hpp"
 #include "util.hpp"
@@ -44,7 +48,8 @@ template <int TS, int NT, int PPT, bool WG, int B, class Pix>
 __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, const Ws &ws, const Sizes &sz,
                                          uint32_t tile, int t, FwdLds<B> &L, float *__restrict__ image,
                                          float *__restrict__ t_final, uint32_t *__restrict__ last_pos,
-                                         uint32_t *__restrict__ n_contrib, Pix pix) {
+                                         uint32_t *__restrict__ n_contrib, const LossArgs &la, float &acc,
+                                         Pix pix) {
   const int v = view_of_tile(views, sz.n_views, tile);
   const ViewInfo vi = views[v];
   const uint32_t lt = tile - vi.tile_base;
@@ -129,13 +134,42 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
       const uint32_t hw = (uint32_t)vi.w * (uint32_t)vi.h;
       const uint32_t pixi = (uint32_t)py[p] * (uint32_t)vi.w + (uint32_t)px[p];
       float *img = image + (size_t)3 * vi.pix_off;
-      img[pixi] = C0[p] + T[p] * sz.bg[0];
-      img[hw + pixi] = C1[p] + T[p] * sz.bg[1];
-      img[2 * hw + pixi] = C2[p] + T[p] * sz.bg[2];
+      const float c0 = C0[p] + T[p] * sz.bg[0], c1 = C1[p] + T[p] * sz.bg[1], c2 = C2[p] + T[p] * sz.bg[2];
+      img[pixi] = c0;
+      img[hw + pixi] = c1;
+      img[2 * hw + pixi] = c2;
+      if (la.target) {
+        const float *tg = la.target + (size_t)3 * vi.pix_off;
+        float *dl = la.dl + (size_t)3 * vi.pix_off;
+        const float d0 = c0 - tg[pixi], d1 = c1 - tg[hw + pixi], d2 = c2 - tg[2 * hw + pixi];
+        auto sgn = [&](float d) { return d > 0.0f ? la.inv_n : (d < 0.0f ? -la.inv_n : 0.0f); };
+        dl[pixi] = sgn(d0);
+        dl[hw + pixi] = sgn(d1);
+        dl[2 * hw + pixi] = sgn(d2);
+        acc += (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+      }
       t_final[vi.pix_off + pixi] = T[p];
       last_pos[vi.pix_off + pixi] = last[p];
       n_contrib[vi.pix_off + pixi] = cnt[p];
     }
+  }
+}
+
+// Sum of the loss accumulators of a workgroup of NW waves into its partial
+// slot: a butterfly per wave, then the waves in order (every thread of the
+// workgroup must take part).
+template <int NW>
+__device__ __forceinline__ void loss_partial(const LossArgs &la, float acc, float *red) {
+  if (!la.target) return;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (lane_id() == 0) red[wave_id()] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += red[w];
+    la.part[blockIdx.x] = s;
   }
 }
 
@@ -152,27 +186,30 @@ union FwdLds16 {
 __global__ __launch_bounds__(256) void k_raster_fwd16(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
                                                       float *__restrict__ image, float *__restrict__ t_final,
                                                       uint32_t *__restrict__ last_pos,
-                                                      uint32_t *__restrict__ n_contrib) {
+                                                      uint32_t *__restrict__ n_contrib, LossArgs la) {
   __shared__ FwdLds16 S;
+  __shared__ float red[4];
   if (ws.scalars[kOverflow]) return;
   const uint32_t n_long = ws.scalars[kNumLong];
   const int t = threadIdx.x;
+  float acc = 0.0f;
   if (blockIdx.x < n_long) {
     fwd_walk<16, 256, 1, true, 256>(views, ws, sz, ws.tile_order[blockIdx.x], t, S.quad, image, t_final, last_pos,
-                                    n_contrib, [](int tt, int, int &x, int &y) {
+                                    n_contrib, la, acc, [](int tt, int, int &x, int &y) {
                                       const int l = tt & 63, w = tt >> 6;
                                       x = (w & 1) * 8 + (l & 7);
                                       y = (w >> 1) * 8 + (l >> 3);
                                     });
   } else {
     const uint32_t i = n_long + (blockIdx.x - n_long) * 4u + (uint32_t)wave_id();
-    if (i >= sz.t_tot) return;
-    fwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], image, t_final,
-                                   last_pos, n_contrib, [](int tt, int p, int &x, int &y) {
-                                     x = (tt & 7) + (p & 1) * 8;
-                                     y = (tt >> 3) + (p >> 1) * 8;
-                                   });
+    if (i < sz.t_tot)
+      fwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], image, t_final,
+                                     last_pos, n_contrib, la, acc, [](int tt, int p, int &x, int &y) {
+                                       x = (tt & 7) + (p & 1) * 8;
+                                       y = (tt >> 3) + (p >> 1) * 8;
+                                     });
   }
+  loss_partial<4>(la, acc, red);
 }
 
 // 8 and 32 px tiles: one workgroup per tile (FwdTile), longest lists first.
@@ -181,30 +218,36 @@ __global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *
                                                                 Sizes sz, float *__restrict__ image,
                                                                 float *__restrict__ t_final,
                                                                 uint32_t *__restrict__ last_pos,
-                                                                uint32_t *__restrict__ n_contrib) {
+                                                                uint32_t *__restrict__ n_contrib, LossArgs la) {
   constexpr int NT = FwdTile<TS>::NT, PPT = FwdTile<TS>::PPT;
   __shared__ FwdLds<NT> S;
+  __shared__ float red[NT / 64];
   if (ws.scalars[kOverflow]) return;
-  if (blockIdx.x >= sz.t_tot) return;
-  fwd_walk<TS, NT, PPT, true, NT>(views, ws, sz, ws.tile_order[blockIdx.x], threadIdx.x, S, image, t_final,
-                                  last_pos, n_contrib,
-                                  [](int tt, int p, int &x, int &y) { fwd_pixel<TS>(tt, p, x, y); });
+  float acc = 0.0f;
+  if (blockIdx.x < sz.t_tot)
+    fwd_walk<TS, NT, PPT, true, NT>(views, ws, sz, ws.tile_order[blockIdx.x], threadIdx.x, S, image, t_final,
+                                    last_pos, n_contrib, la, acc,
+                                    [](int tt, int p, int &x, int &y) { fwd_pixel<TS>(tt, p, x, y); });
+  loss_partial<NT / 64>(la, acc, red);
 }
 
+// Workgroups of the forward launch (the fused loss has one partial per workgroup).
+uint32_t raster_fwd_grid(const Sizes &sz) { return sz.ts == 16 ? sz.t_tot : tile_grid(sz.t_tot); }
+
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
-                       uint32_t *last_pos, uint32_t *n_contrib, hipStream_t st) {
-  const uint32_t grid = tile_grid(sz.t_tot);
+                       uint32_t *last_pos, uint32_t *n_contrib, const LossArgs &la, hipStream_t st) {
+  const uint32_t grid = raster_fwd_grid(sz);
   if (grid == 0) return;
   switch (sz.ts) {
     case 8:
-      k_raster_fwd<8><<<grid, FwdTile<8>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd<8><<<grid, FwdTile<8>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
       break;
     case 32:
-      k_raster_fwd<32><<<grid, FwdTile<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd<32><<<grid, FwdTile<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
       break;
     default:
       // at most t_tot workgroups: one per long tile, then one per four tiles
-      k_raster_fwd16<<<sz.t_tot, 256, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib);
+      k_raster_fwd16<<<grid, 256, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
       break;
   }
 }

@@ -21,7 +21,7 @@ namespace {
 struct Layout {
   size_t scalars, tile_count, tile_start, zero_end;
   size_t block_sums, vis_mask, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
-  size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d, cam_part;
+  size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d, cam_part, loss_part;
   size_t total;
 };
 
@@ -165,6 +165,7 @@ Layout make_layout(const Sizes &s) {
   put(L.partials, (size_t)std::max(s.cap_pairs, s.cap_rec) * 48);
   put(L.g2d, (size_t)s.cap_rec * 48);
   put(L.cam_part, (size_t)cam_chunks(s.cap_rec) * (size_t)s.n_views * 48);
+  put(L.loss_part, (size_t)raster_fwd_grid(s) * 4);
   L.total = o;
   return L;
 }
@@ -205,6 +206,13 @@ MutPtrs mut_ptrs(const gsr_adam_moments *g) {
 }
 
 bool any_null(const MutPtrs &p) { return !p.mean || !p.log_scale || !p.quat || !p.opacity_logit || !p.sh; }
+
+// Pixels of all planned views.
+int64_t total_px(const gsr_ctx *c) {
+  if (c->views.empty()) return 0;
+  const ViewInfo &v = c->views.back();
+  return (int64_t)v.pix_off + (int64_t)v.w * v.h;
+}
 
 float *cam_part(const gsr_ctx *c, void *base) { return reinterpret_cast<float *>(static_cast<char *>(base) + c->lay.cam_part); }
 
@@ -326,8 +334,9 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   return GSR_OK;
 }
 
-gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                              void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, void *stream) {
+static gsr_status forward_common(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                 void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, const LossArgs &la,
+                                 void *stream) {
   gsr_status st = check_common(c, cams, n_views, ws_base, ws_bytes);
   if (st != GSR_OK) return st;
   if ((st = check_gauss(c, g)) != GSR_OK) return st;
@@ -351,7 +360,33 @@ gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_came
   }
   {
     StageTimer tm(c, GSR_STAGE_RASTER_FWD, s);
-    launch_raster_fwd(c->views_d, ws, c->sz, out->image, out->t_final, out->last_pos, out->n_contrib, s);
+    launch_raster_fwd(c->views_d, ws, c->sz, out->image, out->t_final, out->last_pos, out->n_contrib, la, s);
+  }
+  GSR_HIP(c, hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                              void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, void *stream) {
+  return forward_common(c, g, cams, n_views, ws_base, ws_bytes, out, LossArgs{nullptr, nullptr, nullptr, 0.0f},
+                        stream);
+}
+
+gsr_status gsr_render_forward_l1(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                 void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, const float *target,
+                                 float *loss_out, float *dL_dimage, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!target || !loss_out || !dL_dimage) return fail(c, GSR_ERR_INVALID_ARG, "target, loss or dL_dimage is NULL");
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  const int64_t n = 3 * total_px(c);
+  float *part = reinterpret_cast<float *>(static_cast<char *>(ws_base) + c->lay.loss_part);
+  const LossArgs la{target, dL_dimage, part, (float)(1.0 / (double)n)};
+  gsr_status st = forward_common(c, g, cams, n_views, ws_base, ws_bytes, out, la, stream);
+  if (st != GSR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    StageTimer tm(c, GSR_STAGE_LOSS, s);
+    launch_l1_final(part, raster_fwd_grid(c->sz), n, loss_out, s);
   }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
@@ -716,7 +751,7 @@ struct InsLayout {
 
 InsLayout ins_layout(const gsr_ctx *c) {
   InsLayout L{};
-  const int64_t px = c->views.empty() ? 0 : (int64_t)c->views.back().pix_off + (int64_t)c->views.back().w * c->views.back().h;
+  const int64_t px = total_px(c);
   const size_t nb = ins_blocks(px);
   L.mask = 0;
   L.counts = align_up((size_t)px);
@@ -773,7 +808,7 @@ gsr_status gsr_log_insert(gsr_ctx *c, const gsr_camera *cams, const float *gt, c
     taps.h[k] = (float)(h[k] * 2.0 / hm);
   }
   taps.R = R;
-  const int64_t px = (int64_t)c->views.back().pix_off + (int64_t)c->views.back().w * c->views.back().h;
+  const int64_t px = total_px(c);
   char *b = static_cast<char *>(ws);
   launch_log_insert(c->views_d, c->n_views, ins_tiles(c->views.data(), c->n_views), px,
                     reinterpret_cast<const Cam *>(cams), gt, render, depth, taps, cfg->tau_a, p_gt, p_render,

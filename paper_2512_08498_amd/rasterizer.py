@@ -176,6 +176,28 @@ class Rasterizer:
             self._check(st)
         return out
 
+    def forward_l1(self, params, target, out=None, loss_out=None, dl_out=None, check=True, cams_dev=None):
+        """forward() with the L1 loss against ``target`` fused in: returns
+        (out, loss [1], dL/dimage)."""
+        out = out if out is not None else self.new_fwd_out()
+        _check_param("target", target, (3 * self.total_px,), self.device)
+        loss_out = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=self.device)
+        dl_out = dl_out if dl_out is not None else torch.empty_like(out["image"])
+        g = self._gaussians(params)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self._check(self.lib.gsr_render_forward_l1(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
+                                                   self.ws_bytes, C.byref(self._fwd_struct(out)), _vp(target),
+                                                   _vp(loss_out), _vp(dl_out), self.stream()))
+        if check:
+            st = self.lib.gsr_check(self.ctx, _vp(self.workspace), self.stream())
+            if st == L.GSR_ERR_CAPACITY:
+                rec, pairs, _ = self.required_capacity()
+                self._plan(max(int(rec * 1.25) + 1024, self.capacity[0]), max(int(pairs * 1.25) + 4096,
+                                                                                self.capacity[1]))
+                return self.forward_l1(params, target, out, loss_out, dl_out, True, cams_dev)
+            self._check(st)
+        return out, loss_out, dl_out
+
     def required_capacity(self):
         r, p, t = C.c_int64(), C.c_int64(), C.c_int64()
         self._check(self.lib.gsr_required_capacity(self.ctx, _vp(self.workspace), C.byref(r), C.byref(p),

@@ -302,3 +302,29 @@ def test_edge_screen_filling_gaussians_and_stack():
     sc = scene([[0, 0, 3.0 + 0.01 * i] for i in range(n)], [[0.5, 0.4, 0.3]] * n, [[1, 0, 0, 0]] * n,
                [logit(0.3)] * n, colours=[[0.2 + 0.02 * i, 0.5, 0.7] for i in range(n)])
     _edge_check(sc, [camera(60.0, 96, 64)])
+
+
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_forward_with_fused_l1_loss(ts):
+    """gsr_render_forward_l1: the same image and dL/dimage bit for bit as
+    the forward followed by gsr_l1_loss, and the same loss up to the order of
+    the float sums; against the oracle's loss on its own image."""
+    from oracle.loss64 import l1_loss
+    from oracle.render64 import render
+
+    scene, cams = mini_rig()
+    rng = np.random.default_rng(77)
+    targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
+    tgt = torch.from_numpy(np.concatenate([t.reshape(-1) for t in targets])).cuda()
+    rast, params, out = render_gpu(scene, cams, ts=ts, bg=(0.1, 0.2, 0.3))
+    loss_a, dl_a = rast.l1_loss(out["image"], tgt)
+    out_b, loss_b, dl_b = rast.forward_l1(params, tgt)
+    torch.cuda.synchronize()
+    assert torch.equal(out_b["image"], out["image"])
+    assert torch.equal(out_b["t_final"], out["t_final"])
+    assert torch.equal(dl_b, dl_a)
+    assert abs(loss_b.item() - loss_a.item()) <= 1e-6 * abs(loss_a.item())
+    ref = render(scene, cams, bg=(0.1, 0.2, 0.3))
+    ref_loss, _ = l1_loss([r["image"] for r in ref], targets)
+    log(f"ts {ts}: fused {loss_b.item():.8f}, separate {loss_a.item():.8f}, oracle {ref_loss:.8f}")
+    assert abs(loss_b.item() - ref_loss) <= 1e-5 * ref_loss
