@@ -59,7 +59,7 @@ struct AdamArgs {
 
 void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
-                       const Sizes &sz, int sh_degree, hipStream_t st);
+                       const Sizes &sz, int sh_degree, uint32_t *zero, uint64_t n_zero, hipStream_t st);
 void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st);
 void launch_tile_csr(const Ws &ws, const Sizes &sz, uint32_t *csr, hipStream_t st);
@@ -69,7 +69,7 @@ void launch_l1_final(const float *partials, uint32_t nb, int64_t n, float *loss,
 uint32_t raster_fwd_grid(const Sizes &sz);
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);
-void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st);
+void launch_reduce_pairs(const Ws &ws, const Sizes &sz, int32_t *step, hipStream_t st);
 void launch_pre_bwd(const GaussPtrs &gp, const Cam *cams, const Ws &ws, const Sizes &sz, int sh_degree,
                     const MutPtrs *grads, int accumulate, const AdamArgs *adam, float4 *cam_rec, hipStream_t st);
 uint32_t cam_chunks(uint32_t cap_rec);

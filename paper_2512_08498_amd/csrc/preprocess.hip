@@ -28,10 +28,14 @@ __device__ __forceinline__ uint32_t rect_area(const Proj &P, int ts_shift) {
   return w * h;
 }
 
+// Also clears the n_zero words at `zero` (the forward's counters and tile
+// ranges, which no kernel before the scan reads), saving a launch.
 __global__ __launch_bounds__(kPreBlock) void k_pre_count(GaussPtrs gp, const Cam *__restrict__ cams,
-                                                         Ws ws, Sizes sz, int ts_shift) {
+                                                         Ws ws, Sizes sz, int ts_shift, uint32_t *__restrict__ zero,
+                                                         uint64_t n_zero) {
   __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
   const int64_t g = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  for (uint64_t i = (uint64_t)g; i < n_zero; i += (uint64_t)gridDim.x * kPreBlock) zero[i] = 0u;
   uint32_t recs = 0, pairs = 0;
   if (g < sz.n) {
     float m3[3], l3[3], q4[4];
@@ -197,12 +201,17 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
   }
 }
 
+void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
+
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
-                       const Sizes &sz, int sh_degree, hipStream_t st) {
+                       const Sizes &sz, int sh_degree, uint32_t *zero, uint64_t n_zero, hipStream_t st) {
   (void)views;
   const int ts_shift = sz.ts == 8 ? 3 : (sz.ts == 16 ? 4 : 5);
-  if (sz.n_blocks == 0) return;
-  k_pre_count<<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift);
+  if (sz.n_blocks == 0) {
+    launch_zero(zero, n_zero, st);
+    return;
+  }
+  k_pre_count<<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift, zero, n_zero);
   k_scan_blocks<<<1, 1024, 0, st>>>(ws, sz);
   switch (sh_degree) {
     case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;

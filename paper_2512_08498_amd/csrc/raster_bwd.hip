@@ -332,7 +332,10 @@ __device__ __forceinline__ void add_partial(const float4 *__restrict__ src, floa
   v[8] += z.x;
 }
 
-__global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws) {
+// step (optional): the Adam step counter, incremented here (before the
+// per-Gaussian kernel that reads it) rather than by a launch of its own.
+__global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
+  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
   if (ws.scalars[kOverflow]) return;
   const uint32_t nrec = ws.scalars[kNumRecords];
   const int lane = lane_id();
@@ -399,9 +402,9 @@ void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, con
   }
 }
 
-void launch_reduce_pairs(const Ws &ws, const Sizes &sz, hipStream_t st) {
+void launch_reduce_pairs(const Ws &ws, const Sizes &sz, int32_t *step, hipStream_t st) {
   const uint32_t blocks = std::min<uint32_t>((sz.cap_rec + 255) / 256, 4096u);
-  k_reduce_pairs<<<std::max(blocks, 1u), 256, 0, st>>>(ws);
+  k_reduce_pairs<<<std::max(blocks, 1u), 256, 0, st>>>(ws, step);
 }
 
 }  // namespace gsr

@@ -347,8 +347,8 @@ static gsr_status forward_common(gsr_ctx *c, const gsr_gaussians *g, const gsr_c
   const Cam *cm = reinterpret_cast<const Cam *>(cams);
   {
     StageTimer tm(c, GSR_STAGE_PREPROCESS, s);
-    launch_zero(ws.scalars, (c->lay.zero_end - c->lay.scalars) / 4, s);
-    launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, s);
+    launch_preprocess(gauss_ptrs(g), cm, c->views_d, ws, c->sz, c->sh_degree, ws.scalars,
+                      (c->lay.zero_end - c->lay.scalars) / 4, s);
   }
   {
     StageTimer tm(c, GSR_STAGE_SORT, s);
@@ -432,7 +432,7 @@ gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_cam
   }
   {
     StageTimer tm(c, GSR_STAGE_REDUCE, s);
-    launch_reduce_pairs(ws, c->sz, s);
+    launch_reduce_pairs(ws, c->sz, nullptr, s);
   }
   {
     StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
@@ -512,11 +512,10 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   }
   {
     StageTimer tm(c, GSR_STAGE_REDUCE, s);
-    launch_reduce_pairs(ws, c->sz, s);
+    launch_reduce_pairs(ws, c->sz, step_dev, s);  // also advances the Adam step
   }
   {
     StageTimer tm(c, GSR_STAGE_PRE_BWD, s);
-    launch_step_inc(step_dev, s);
     launch_pre_bwd(gauss_ptrs(g), reinterpret_cast<const Cam *>(cams), ws, c->sz, c->sh_degree, &gr, 0, &a,
                    cam_rec, s);
     if (cam_rec) launch_cam_grads(ws, c->sz, cam_rec, cam_part(c, ws_base), grads_out->camera, 0, s);
