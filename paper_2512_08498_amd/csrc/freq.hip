@@ -82,10 +82,34 @@ struct Roots<7> {
   }
 };
 
-// In-register radix-P DFT with the forward sign.
+// In-register radix-P DFT with the forward sign.  Radices 3 and 5 use the
+// symmetric forms: with s_k = x_k + x_{P-k} and d_k = x_k - x_{P-k},
+// X_q = x_0 + sum_k cos(2 pi k q / P) s_k - i sum_k sin(2 pi k q / P) d_k.
 template <int P>
 __device__ __forceinline__ void dft(float2 *v) {
-  if constexpr (P == 2) {
+  if constexpr (P == 3) {
+    constexpr float s1 = 0.86602540378443865f;  // sin(2 pi / 3)
+    const float2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const float2 a = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
+    const float2 b = make_float2(s1 * d.y, -s1 * d.x);  // -i sin(2 pi / 3) d
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(a, b);
+    v[2] = csub(a, b);
+  } else if constexpr (P == 5) {
+    constexpr float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;  // cos(2 pi / 5), cos(4 pi / 5)
+    constexpr float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;   // sin(2 pi / 5), sin(4 pi / 5)
+    const float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    const float2 b1 = make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+    const float2 b2 = make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, cmi(b1));
+    v[4] = csub(a1, cmi(b1));
+    v[2] = cadd(a2, cmi(b2));
+    v[3] = csub(a2, cmi(b2));
+  } else if constexpr (P == 2) {
     const float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -131,22 +155,25 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int N, int cnt, int Ns, c
   const int m = N / P;
   const int total = cnt * m;
   const int tstep = N / (Ns * P);
-  const float inv_m = 1.0f / (float)m, inv_ns = 1.0f / (float)Ns;
+  const float inv_ns = 1.0f / (float)Ns;
+  const bool first = Ns == 1;  // k = 0: no twiddles, no division
   float2 v[kMaxB][P];
   int dst[kMaxB];
 #pragma unroll
   for (int i = 0; i < kMaxB; ++i) {
     const int b = threadIdx.x + i * T;
     if (b < total) {
-      const int seq = fdiv(b, m, inv_m);
+      const int seq = (b >= m ? 1 : 0) + (b >= 2 * m ? 1 : 0);  // cnt <= 3
       const int j = b - seq * m;
-      const int jq = fdiv(j, Ns, inv_ns);
+      const int jq = first ? j : fdiv(j, Ns, inv_ns);
       const int k = j - jq * Ns;
       const float2 *src = buf + seq * N + j;
 #pragma unroll
       for (int r = 0; r < P; ++r) v[i][r] = src[r * m];
+      if (!first) {
 #pragma unroll
-      for (int r = 1; r < P; ++r) v[i][r] = cmul(v[i][r], tw[k * r * tstep]);
+        for (int r = 1; r < P; ++r) v[i][r] = cmul(v[i][r], tw[k * r * tstep]);
+      }
       dft<P>(v[i]);
       dst[i] = seq * N + jq * Ns * P + k;
     }
