@@ -17,11 +17,88 @@
 // which is the conic quadratic form -(a dx^2 + 2 b dx dy + c dy^2)/2 written
 // as a sum of squares, free of the cancellation the expanded form suffers
 // for elongated footprints.
+//
+// The tile lists hold every tile of a record's binning rectangle, but the
+// alpha >= 1/255 ellipse of an elongated or tilted footprint misses many of
+// them.  The backward therefore compacts each batch in LDS to the records
+// that can reach the threshold somewhere in the tile (tile_reaches); the
+// others cost one lane's test instead of box tests and failed alpha
+// evaluations in every pixel slot.  The test is conservative, so the
+// composited sequence of every pixel, and with it every gradient bit, is
+// unchanged.  (In the forward the test's registers cost more occupancy than
+// the skipped records save.)
 #pragma once
 
 #include "common.hpp"
+#include "util.hpp"
 
 namespace gsr {
+
+// Whether the record (box, p1, p2 of its payload) can reach alpha >= 1/255 at
+// a pixel of the tile whose pixels span [x0, x0 + ts - 1] x [y0, y0 + ts - 1].
+// With A = -qa, C = -qc, k = qb the falloff is f = A (dx + k dy)^2 + C dy^2
+// (alpha = opacity 2^-f), convex, and a pixel composites only if
+// f <= log2(255 opacity).  Its exact minimum over the rectangle tile ∩ box
+// (continuous, so it bounds every pixel centre in it) is 0 when the
+// rectangle holds the centre, else the least of the four edge minima: at
+// fixed dy the minimiser is dx = -k dy, at fixed dx it is
+// dy = -A k dx / (A k^2 + C), each clamped to the edge.  The record is
+// dropped only if that minimum exceeds the threshold by a margin covering the
+// rounding of this evaluation and of the per-pixel one (a relative 2^-18 of
+// the largest value f takes on the rectangle, plus 1/16 for the hardware
+// exp2 and log2); NaN keeps it.
+__device__ __forceinline__ bool tile_reaches(const float4 box, const float4 p1, const float4 p2, float x0, float y0,
+                                             float ts) {
+  const float X0 = fmaxf(x0, box.x), X1 = fminf(x0 + (ts - 1.0f), box.y);
+  const float Y0 = fmaxf(y0, box.z), Y1 = fminf(y0 + (ts - 1.0f), box.w);
+  if (X0 > X1 || Y0 > Y1) return false;
+  const float dx0 = (X0 - box.x) - p1.x, dx1 = (X1 - box.x) - p1.x;
+  const float dy0 = (Y0 - box.z) - p1.y, dy1 = (Y1 - box.z) - p1.y;
+  const float A = -p1.z, k = p1.w, C = -p2.x;
+  auto f = [&](float dx, float dy) {
+    const float u = fmaf(k, dy, dx);
+    return fmaf(A, u * u, C * (dy * dy));
+  };
+  auto clampf = [](float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); };
+  float fmin = 0.0f;
+  if (!(dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f)) {
+    const float r = (A * k) / fmaf(A * k, k, C);
+    const float e0 = f(clampf(-k * dy0, dx0, dx1), dy0), e1 = f(clampf(-k * dy1, dx0, dx1), dy1);
+    const float e2 = f(dx0, clampf(-r * dx0, dy0, dy1)), e3 = f(dx1, clampf(-r * dx1, dy0, dy1));
+    fmin = fminf(fminf(e0, e1), fminf(e2, e3));
+  }
+  const float mx = fmaxf(fabsf(dx0), fabsf(dx1)), my = fmaxf(fabsf(dy0), fabsf(dy1));
+  const float um = fmaf(fabsf(k), my, mx);
+  const float big = fmaf(A, um * um, C * (my * my));
+  const float thr = __builtin_amdgcn_logf(p2.y) + 0x1.ffa37cp+2f;  // log2(opacity) + log2(255)
+  return !(fmin > thr + (0.0625f + 0x1p-18f * big));
+}
+
+// Slot of this thread's record in the compacted batch: the kept records
+// numbered in thread order.  A workgroup (WG) exchanges its NW per-wave
+// counts through wc with one barrier; a single wave needs none.  Returns the
+// slot (meaningful where keep) and the number kept in `total`.  Every thread
+// of the group must call it.
+template <bool WG, int NW>
+__device__ __forceinline__ uint32_t compact_slot(bool keep, uint32_t *wc, uint32_t &total) {
+  const uint64_t b = __ballot(keep);
+  const uint32_t before = (uint32_t)__popcll(b & lanemask_lt());
+  if (!WG) {
+    total = (uint32_t)__popcll(b);
+    return before;
+  }
+  if (lane_id() == 0) wc[wave_id()] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = wc[w];
+    off += w < wave_id() ? c : 0u;
+    tot += c;
+  }
+  total = tot;
+  return off + before;
+}
 
 // Forward at 8 and 32 px (and for long lists at 16 px): all waves of the
 // workgroup share the tile's LDS batch, each wave an 8 x 8 block with one

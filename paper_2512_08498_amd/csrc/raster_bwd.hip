@@ -10,6 +10,8 @@
 // and, unless alpha hit the 0.99 cap, dL/dopacity and dL/dq through
 // alpha = opacity 2^q, then dL/d(qa, qb, qc, offx, offy) through q.
 //
+// Each batch is compacted to the records whose alpha >= 1/255 ellipse
+// reaches the tile (the others get zero partials at once).
 // The 9 per-entry gradients are summed over each wave by DPP row reductions
 // (skipped when no lane of the wave touched the entry), combined over the
 // waves in LDS, and written once per (record, tile) into that pair's slot --
@@ -55,9 +57,9 @@ __device__ __forceinline__ uint32_t group_max(uint32_t x, uint32_t *red) {
 template <int B, int NW>
 struct BwdLds {
   float4 p0[B], p1[B], p2[B], p3[B];
-  uint32_t out[B];
+  uint32_t out[B], pos[B];
   float g[B * NW * 9];
-  uint32_t red[4];
+  uint32_t red[4], wc[4];
 };
 
 // The adjoint walk over one tile's list by a group of NT threads (a
@@ -76,6 +78,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
   const uint32_t tx = lt % (uint32_t)vi.tiles_x, ty = lt / (uint32_t)vi.tiles_x;
   const uint32_t start = ws.tile_start[tile], n = ws.tile_count[tile];
   const uint32_t nrec = ws.scalars[kNumRecords];
+  const float ox = (float)(tx * TS), oy = (float)(ty * TS);
   if (n == 0) return;
 
   float fx[PPT], fy[PPT], T[PPT], g0[PPT], g1[PPT], g2[PPT], R0[PPT], R1[PPT], R2[PPT];
@@ -157,21 +160,31 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
     const uint32_t lo = batch_lo(hi);
     const uint32_t m = hi - lo;
     group_sync<WG>();
-    if ((uint32_t)t < m) {
-      L.p0[t] = f0;
-      L.p1[t] = f1;
-      L.p2[t] = f2;
-      L.p3[t] = f3;
-      L.out[t] = fslot;
+    // compact the batch to the records that can composite in this tile; the
+    // others get zero gradients here
+    const bool keep = (uint32_t)t < m && tile_reaches(f0, f1, f2, ox, oy, (float)TS);
+    uint32_t mc;
+    const uint32_t cs = compact_slot<WG, NW>(keep, L.wc, mc);
+    if (keep) {
+      L.p0[cs] = f0;
+      L.p1[cs] = f1;
+      L.p2[cs] = f2;
+      L.p3[cs] = f3;
+      L.out[cs] = fslot;
+      L.pos[cs] = lo + (uint32_t)t;
+    } else if ((uint32_t)t < m) {
+      ws.partials[(size_t)fslot * 3 + 0] = zero4;
+      ws.partials[(size_t)fslot * 3 + 1] = zero4;
+      ws.partials[(size_t)fslot * 3 + 2] = zero4;
     }
     if (lo > 0) {
       const uint32_t lo2 = batch_lo(lo);
       if ((uint32_t)t < lo - lo2) fetch(lo2);
     }
-    for (int k = t; k < B * NW * 9; k += NT) L.g[k] = 0.0f;
+    for (uint32_t k = t; k < mc * NW * 9; k += NT) L.g[k] = 0.0f;
     group_sync<WG>();
-    for (int jj = (int)m - 1; jj >= 0; --jj) {
-      const uint32_t pos = lo + (uint32_t)jj;
+    for (int jj = (int)mc - 1; jj >= 0; --jj) {
+      const uint32_t pos = L.pos[jj];
       const float4 box = L.p0[jj];
       bool in[PPT];
       bool any_in = false;
@@ -240,7 +253,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       }
     }
     group_sync<WG>();
-    for (uint32_t e = t; e < m; e += NT) {
+    for (uint32_t e = t; e < mc; e += NT) {
       float s9[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) s9[c] = 0.0f;

@@ -15,7 +15,7 @@ from gpu_helpers import device_params, grads_to_host, host_outputs, last_gaussia
 from oracle.binning import tile_lists
 from oracle.grad64 import grad64
 from oracle.render64 import render
-from tiny_scenes import mini_rig
+from tiny_scenes import mini_rig, needles
 from workloads import make_config
 
 pytestmark = pytest.mark.gpu
@@ -85,10 +85,10 @@ def _compare_grads(gpu, ora, tol=GRAD_TOL):
         assert rel <= tol, k
 
 
-def _check_backward(scene, cams, targets, ts=16):
+def _check_backward(scene, cams, targets, ts=16, **kw):
     oracle = render(scene, cams)
     cots = _masked_cotangent(oracle, targets)
-    rast, params, out = render_gpu(scene, cams, ts=ts)
+    rast, params, out = render_gpu(scene, cams, ts=ts, **kw)
     dl = torch.from_numpy(np.concatenate([c.astype(np.float32).reshape(-1) for c in cots])).cuda()
     grads = rast.backward(params, out, dl)
     torch.cuda.synchronize()
@@ -108,6 +108,20 @@ def test_backward_posed_two_views_sh3():
     targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
     log("backward mini rig")
     _check_backward(scene, cams, targets)
+
+
+@pytest.mark.parametrize("ts,long_list", [(16, 1024), (16, 0), (8, 1024), (32, 1024)])
+def test_needles_forward_and_backward(ts, long_list):
+    """Elongated footprints near the opacity threshold: the backward drops,
+    per tile, the records whose alpha >= 1/255 ellipse misses it (about 40%
+    of this scene's pairs), in the one-wave and the workgroup walks
+    (long_list 0 sends every tile to the workgroup walk)."""
+    scene, cams = needles()
+    log(f"needles ts={ts} long_list={long_list}")
+    _check_forward(scene, cams, ts)
+    rng = np.random.default_rng(3)
+    targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
+    _check_backward(scene, cams, targets, ts, long_list=long_list)
 
 
 def _oracle_evaluations(scene, cams, oracle):

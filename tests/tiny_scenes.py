@@ -53,3 +53,18 @@ def mini_rig(seed=7, n=300, degree=3, w=96, h=64):
     c1 = np.array([0.3, -0.1, 0.2])
     cams = [camera(80.0, w, h), camera(80.0, w, h, cx=w / 2 + 3.25, cy=h / 2 - 1.5, R=R1, t=-R1 @ c1, fy=84.0)]
     return sc, cams
+
+
+def needles(seed=5, n=400, w=96, h=64):
+    """Needle-like footprints (about 50:1 axes, every orientation), half of
+    them with opacities just above 1/255: most tiles of their binning
+    rectangles lie outside the alpha >= 1/255 ellipse, and many ellipses end
+    close to a tile edge."""
+    rng = np.random.default_rng(seed)
+    means = np.stack([rng.uniform(-2.0, 2.0, n), rng.uniform(-1.4, 1.4, n), rng.uniform(3.0, 6.0, n)], 1)
+    ls = np.stack([rng.uniform(-1.6, -0.9, n), rng.normal(-5.0, 0.2, n), rng.normal(-5.0, 0.2, n)], 1)
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = np.where(rng.random(n) < 0.5, rng.uniform(1.05 / 255, 4.0 / 255, n), rng.uniform(0.05, 0.9, n))
+    col = rng.uniform(0.0, 1.0, (n, 3))
+    return scene(means, ls, q, [logit(p) for p in op], colours=col), [camera(80.0, w, h)]
