@@ -50,9 +50,9 @@ __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t 
 
 // Emission: each wave takes 64 consecutive records of the depth order; their
 // pairs form one contiguous range (offs[i] is the first pair of sorted record
-// i, kept per record for the backward).  A record of at most kEmitSmall pairs
-// is written by its own lane, stepping through its tile rectangle; the lanes'
-// stores fall into that one range.  Bigger footprints are written by the
+// i).  A record of at most kEmitSmall pairs is written by its own lane,
+// stepping through its tile rectangle; the lanes' stores fall into that one
+// range.  Bigger footprints are written by the
 // whole wave, 64 pairs per step.
 constexpr uint32_t kEmitSmall = 8;
 
@@ -79,7 +79,6 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
       tbase = vi.tile_base;
       tpitch = (uint32_t)vi.tiles_x;
       off = offs[i];
-      ws.rec_pairoff[rec] = off;
       if (off + cnt > sz.cap_pairs) {  // inconsistent pair offsets
         ws.scalars[kOverflow] = 3u;
         cnt = 0;

@@ -45,7 +45,7 @@ struct Ws {
   float4 *rec_payload;      // [cap_rec][4] raster payload, see RecPayload
   uint32_t *rec_g;          // [cap_rec] Gaussian index
   uint32_t *rec_view;       // [cap_rec] view index
-  uint32_t *rec_pairoff;    // [cap_rec] first pair of the record (record-major)
+  uint32_t *rec_pairoff;    // [cap_rec] first gradient slot of the record (records in order, tiles row-major)
   uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t *rec_zbits;      // [cap_rec] depth bits
   uint32_t *rec_tmp;        // [5][cap_rec] depth sort of the records, pair offsets

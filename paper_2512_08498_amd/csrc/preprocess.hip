@@ -106,99 +106,114 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
   uint32_t tr;
   const uint2 base = ws.block_sums[blockIdx.x];
   uint32_t rec = base.x + block_excl_scan<kPreBlock>(recs, s_scan, tr);
-  if (!live) return;
-  ws.rec_start[g] = rec;
-  if (g == sz.n - 1) ws.rec_start[sz.n] = rec + recs;
-  if (recs == 0) return;
-
-  float sh[K][3];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) sh[k][ch] = gp.sh[((int64_t)k * 3 + ch) * sz.n + g];
-  const float op = 1.0f / (1.0f + expf(-gp.opacity_logit[g]));
-
-  float m3[3], l3[3], q4[4];
-  load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
-  for (uint32_t wd = 0; wd < sz.vis_words; ++wd)
-    for (uint64_t bits = ws.vis_mask[(int64_t)wd * sz.n + g]; bits; bits &= bits - 1) {
-    const int v = (int)(wd * 64u) + __ffsll((unsigned long long)bits) - 1;
-    const Cam c = load_cam(cams, v);
-    Proj P;
-    project_spec(m3, l3, q4, c, P);
-    // 2D mean in float64 (the pixel grid is ~2^11 wide, so a float32
-    // projection would be off by up to ~1e-4 px); stored as the offset from
-    // the box corner, which float32 represents to ~1e-7 px.
-    const double xd = ((double)c.R[0] * m3[0] + (double)c.R[1] * m3[1]) + (double)c.R[2] * m3[2] + c.t[0];
-    const double yd = ((double)c.R[3] * m3[0] + (double)c.R[4] * m3[1]) + (double)c.R[5] * m3[2] + c.t[1];
-    const double zd = ((double)c.R[6] * m3[0] + (double)c.R[7] * m3[1]) + (double)c.R[8] * m3[2] + c.t[2];
-    const double mux = (double)c.fx * (xd / zd) + (double)c.cx, muy = (double)c.fy * (yd / zd) + (double)c.cy;
-    // The compositing kernels test the box of d^2 <= 2 ln(255 opacity)
-    // instead of the binning box: outside it alpha < 1/255 (for a pixel
-    // centre dx from the mean, d^2 >= dx^2 / S_xx), so the same entries are
-    // composited.  The 0.01 margin in d^2 covers the rounding of the kernels'
-    // d^2 and of this box.  The binning (tile lists) keeps the full box.
-    float bi0 = (float)P.i0, bi1 = (float)P.i1, bj0 = (float)P.j0, bj1 = (float)P.j1;
-    const float keff = 2.0f * logf(255.0f * op) + 0.01f;
-    if (keff < kSupportK) {
-      if (!(keff > 0.0f)) {  // opacity below 1/255: nothing can composite
-        bi0 = bj0 = 1.0f;
-        bi1 = bj1 = 0.0f;
-      } else {
-        const float hxt = sqrtf(keff * (P.p0 + kDilation)), hyt = sqrtf(keff * (P.p1 + kDilation));
-        bi0 = fmaxf(bi0, ceilf((float)mux - hxt - 0.5f));
-        bi1 = fminf(bi1, floorf((float)mux + hxt - 0.5f));
-        bj0 = fmaxf(bj0, ceilf((float)muy - hyt - 0.5f));
-        bj1 = fminf(bj1, floorf((float)muy + hyt - 0.5f));
-      }
-    }
-    const float offx = (float)(mux - (double)bi0 - 0.5);
-    const float offy = (float)(muy - (double)bj0 - 0.5);
-    // Conic in Cholesky form.  With S = A A^T + 0.3 I:
-    //   d^T S^-1 d = (dx + qb dy)^2 * S_yy / det + dy^2 / S_yy,  qb = -S_xy / S_yy
-    // and det = |a0 x a1|^2 + 0.3 (|a0|^2 + |a1|^2) + 0.09 has no cancellation.
-    const float sxx = P.p0 + kDilation, syy = P.p1 + kDilation;
-    const float sxy = (P.a0[0] * P.a1[0] + P.a0[1] * P.a1[1]) + P.a0[2] * P.a1[2];
-    const float cx_ = P.a0[1] * P.a1[2] - P.a0[2] * P.a1[1];
-    const float cy_ = P.a0[2] * P.a1[0] - P.a0[0] * P.a1[2];
-    const float cz_ = P.a0[0] * P.a1[1] - P.a0[1] * P.a1[0];
-    const float det = (cx_ * cx_ + cy_ * cy_ + cz_ * cz_) + kDilation * (P.p0 + P.p1) + kDilation * kDilation;
-    (void)sxx;
-    const float qa = -kHalfLog2e * (syy / det);
-    const float qb = -sxy / syy;
-    const float qc = -kHalfLog2e / syy;
-    // view-dependent colour
-    const float cxw = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
-    const float cyw = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
-    const float czw = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
-    const float dx = m3[0] - cxw, dy = m3[1] - cyw, dz = m3[2] - czw;
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    float Y[16];
-    sh_basis(dx * inv, dy * inv, dz * inv, DEG, Y);
-    float rgb[3];
-    uint32_t pass = 0;  // bit ch: colour channel ch not clamped (gradient passes)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float s = 0.5f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s += sh[k][ch] * Y[k];
-      rgb[ch] = fmaxf(s, 0.0f);
-      pass |= (s >= 0.0f ? 1u : 0u) << ch;
-    }
-    ws.rec_payload[(size_t)rec * 4 + 0] = make_float4(bi0, bi1, bj0, bj1);
-    ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
-    ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
-    ws.rec_payload[(size_t)rec * 4 + 3] =
-        make_float4(rgb[2], __uint_as_float((uint32_t)P.i0 | ((uint32_t)P.i1 << 16)),
-                    __uint_as_float((uint32_t)P.j0 | ((uint32_t)P.j1 << 16)), __uint_as_float(pass));
-    const int tx0 = P.i0 >> ts_shift, tx1 = P.i1 >> ts_shift;
-    const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
-    ws.rec_g[rec] = (uint32_t)g;
-    ws.rec_view[rec] = (uint32_t)v;
-    ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
-    ws.rec_zbits[rec] = P.zbits;
-    rec += 1;
+  const uint32_t rec0 = rec;
+  uint32_t pairs = 0;
+  if (live) {
+    ws.rec_start[g] = rec;
+    if (g == sz.n - 1) ws.rec_start[sz.n] = rec + recs;
   }
+  if (live && recs > 0) {
+    float sh[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) sh[k][ch] = gp.sh[((int64_t)k * 3 + ch) * sz.n + g];
+    const float op = 1.0f / (1.0f + expf(-gp.opacity_logit[g]));
+
+    float m3[3], l3[3], q4[4];
+    load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+    for (uint32_t wd = 0; wd < sz.vis_words; ++wd)
+      for (uint64_t bits = ws.vis_mask[(int64_t)wd * sz.n + g]; bits; bits &= bits - 1) {
+      const int v = (int)(wd * 64u) + __ffsll((unsigned long long)bits) - 1;
+      const Cam c = load_cam(cams, v);
+      Proj P;
+      project_spec(m3, l3, q4, c, P);
+      // 2D mean in float64 (the pixel grid is ~2^11 wide, so a float32
+      // projection would be off by up to ~1e-4 px); stored as the offset from
+      // the box corner, which float32 represents to ~1e-7 px.
+      const double xd = ((double)c.R[0] * m3[0] + (double)c.R[1] * m3[1]) + (double)c.R[2] * m3[2] + c.t[0];
+      const double yd = ((double)c.R[3] * m3[0] + (double)c.R[4] * m3[1]) + (double)c.R[5] * m3[2] + c.t[1];
+      const double zd = ((double)c.R[6] * m3[0] + (double)c.R[7] * m3[1]) + (double)c.R[8] * m3[2] + c.t[2];
+      const double mux = (double)c.fx * (xd / zd) + (double)c.cx, muy = (double)c.fy * (yd / zd) + (double)c.cy;
+      // The compositing kernels test the box of d^2 <= 2 ln(255 opacity)
+      // instead of the binning box: outside it alpha < 1/255 (for a pixel
+      // centre dx from the mean, d^2 >= dx^2 / S_xx), so the same entries are
+      // composited.  The 0.01 margin in d^2 covers the rounding of the kernels'
+      // d^2 and of this box.  The binning (tile lists) keeps the full box.
+      float bi0 = (float)P.i0, bi1 = (float)P.i1, bj0 = (float)P.j0, bj1 = (float)P.j1;
+      const float keff = 2.0f * logf(255.0f * op) + 0.01f;
+      if (keff < kSupportK) {
+        if (!(keff > 0.0f)) {  // opacity below 1/255: nothing can composite
+          bi0 = bj0 = 1.0f;
+          bi1 = bj1 = 0.0f;
+        } else {
+          const float hxt = sqrtf(keff * (P.p0 + kDilation)), hyt = sqrtf(keff * (P.p1 + kDilation));
+          bi0 = fmaxf(bi0, ceilf((float)mux - hxt - 0.5f));
+          bi1 = fminf(bi1, floorf((float)mux + hxt - 0.5f));
+          bj0 = fmaxf(bj0, ceilf((float)muy - hyt - 0.5f));
+          bj1 = fminf(bj1, floorf((float)muy + hyt - 0.5f));
+        }
+      }
+      const float offx = (float)(mux - (double)bi0 - 0.5);
+      const float offy = (float)(muy - (double)bj0 - 0.5);
+      // Conic in Cholesky form.  With S = A A^T + 0.3 I:
+      //   d^T S^-1 d = (dx + qb dy)^2 * S_yy / det + dy^2 / S_yy,  qb = -S_xy / S_yy
+      // and det = |a0 x a1|^2 + 0.3 (|a0|^2 + |a1|^2) + 0.09 has no cancellation.
+      const float sxx = P.p0 + kDilation, syy = P.p1 + kDilation;
+      const float sxy = (P.a0[0] * P.a1[0] + P.a0[1] * P.a1[1]) + P.a0[2] * P.a1[2];
+      const float cx_ = P.a0[1] * P.a1[2] - P.a0[2] * P.a1[1];
+      const float cy_ = P.a0[2] * P.a1[0] - P.a0[0] * P.a1[2];
+      const float cz_ = P.a0[0] * P.a1[1] - P.a0[1] * P.a1[0];
+      const float det = (cx_ * cx_ + cy_ * cy_ + cz_ * cz_) + kDilation * (P.p0 + P.p1) + kDilation * kDilation;
+      (void)sxx;
+      const float qa = -kHalfLog2e * (syy / det);
+      const float qb = -sxy / syy;
+      const float qc = -kHalfLog2e / syy;
+      // view-dependent colour
+      const float cxw = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+      const float cyw = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+      const float czw = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+      const float dx = m3[0] - cxw, dy = m3[1] - cyw, dz = m3[2] - czw;
+      const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      float Y[16];
+      sh_basis(dx * inv, dy * inv, dz * inv, DEG, Y);
+      float rgb[3];
+      uint32_t pass = 0;  // bit ch: colour channel ch not clamped (gradient passes)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float s = 0.5f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += sh[k][ch] * Y[k];
+        rgb[ch] = fmaxf(s, 0.0f);
+        pass |= (s >= 0.0f ? 1u : 0u) << ch;
+      }
+      ws.rec_payload[(size_t)rec * 4 + 0] = make_float4(bi0, bi1, bj0, bj1);
+      ws.rec_payload[(size_t)rec * 4 + 1] = make_float4(offx, offy, qa, qb);
+      ws.rec_payload[(size_t)rec * 4 + 2] = make_float4(qc, op, rgb[0], rgb[1]);
+      ws.rec_payload[(size_t)rec * 4 + 3] =
+          make_float4(rgb[2], __uint_as_float((uint32_t)P.i0 | ((uint32_t)P.i1 << 16)),
+                      __uint_as_float((uint32_t)P.j0 | ((uint32_t)P.j1 << 16)), __uint_as_float(pass));
+      const int tx0 = P.i0 >> ts_shift, tx1 = P.i1 >> ts_shift;
+      const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
+      ws.rec_g[rec] = (uint32_t)g;
+      ws.rec_view[rec] = (uint32_t)v;
+      ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+      ws.rec_zbits[rec] = P.zbits;
+      pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      rec += 1;
+    }
+  }
+  // First (record, tile) slot of each record in record order: the gradient
+  // partials of a record's tiles are contiguous and consecutive records'
+  // slots follow each other, so the per-record reduction streams them.
+  uint32_t tp;
+  uint32_t slot = base.y + block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
+  if (live)
+    for (uint32_t r = rec0; r < rec0 + recs; ++r) {
+      const uint2 rc = ws.rec_rect[r];
+      ws.rec_pairoff[r] = slot;
+      slot += ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
+    }
 }
 
 void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
