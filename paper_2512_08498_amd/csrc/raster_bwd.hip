@@ -195,19 +195,20 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       }
       // (wave-uniform) records no pixel of the wave touches cost only the tests
       if (__ballot(any_in) == 0) continue;
-      // q-gradients are accumulated without the ln 2 of d alpha / dq, applied
-      // once to the sums in the epilogue.  The empty asm keeps the zeros
+      // With dq = dL/dalpha alpha (dL/dq without the ln 2 of d alpha / dq)
+      // each pixel adds dq u, dq dy, dq u^2, dq u dy and dq dy^2; the record's
+      // constants qa, qb, qc and ln 2 turn the sums into the payload
+      // gradients once, in the epilogue.  The empty asm keeps the zeros
       // opaque, so the compiler does not re-materialise them on every path
       // through the per-pixel branches.
-      float a_offx = 0.f, a_offy = 0.f, a_qa = 0.f, a_qb = 0.f, a_qc = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f,
+      float a_u = 0.f, a_dy = 0.f, a_qa = 0.f, a_udy = 0.f, a_qc = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f,
             a_b = 0.f;
-      asm volatile("" : "+v"(a_offx), "+v"(a_offy), "+v"(a_qa), "+v"(a_qb), "+v"(a_qc), "+v"(a_o), "+v"(a_r),
+      asm volatile("" : "+v"(a_u), "+v"(a_dy), "+v"(a_qa), "+v"(a_udy), "+v"(a_qc), "+v"(a_o), "+v"(a_r),
                    "+v"(a_g), "+v"(a_b));
       bool any = false;
       if (any_in) {
         const float4 q1 = L.p1[jj], q2 = L.p2[jj];
         const float cb = L.p3[jj].x;
-        const float two_qa = 2.0f * q1.z, two_qc = 2.0f * q2.x;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           if (in[p]) {
@@ -235,19 +236,19 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
               if (oe <= kAlphaMax) {
                 a_o = fmaf(e, dla, a_o);
                 const float dq = dla * alpha;
-                const float t1 = dq * (two_qa * u);
+                const float du = dq * u;
+                a_u += du;
+                a_dy = fmaf(dq, dy, a_dy);
                 a_qa = fmaf(dq, u2, a_qa);
+                a_udy = fmaf(du, dy, a_udy);
                 a_qc = fmaf(dq, dy2, a_qc);
-                a_qb = fmaf(t1, dy, a_qb);
-                a_offx -= t1;
-                a_offy -= fmaf(t1, q1.w, dq * two_qc * dy);
               }
             }
           }
         }
       }
       if (__ballot(any)) {
-        const float v9[9] = {a_offx, a_offy, a_qa, a_qb, a_qc, a_o, a_r, a_g, a_b};
+        const float v9[9] = {a_u, a_dy, a_qa, a_udy, a_qc, a_o, a_r, a_g, a_b};
         const float sum = wave_sum9_packed(v9);  // value l in lane l < 8, value 8 in lane 32
         if (lane < 8 || lane == 32) L.g[((size_t)jj * NW + wv) * 9 + (lane < 8 ? lane : 8)] = sum;
       }
@@ -261,8 +262,13 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       for (int w = 0; w < NW; ++w)
 #pragma unroll
         for (int c = 0; c < 9; ++c) s9[c] += L.g[((size_t)e * NW + w) * 9 + c];
+      // q = qa u^2 + qc dy^2, u = dx + qb dy, dx = ... - offx, dy = ... - offy:
+      //   dL/dqb = 2 qa sum(dq u dy),  dL/doffx = -2 qa sum(dq u),
+      //   dL/doffy = -(2 qa qb sum(dq u) + 2 qc sum(dq dy))   (times ln 2)
       const uint32_t slot = L.out[e];
-      ws.partials[(size_t)slot * 3 + 0] = make_float4(s9[0] * kLn2, s9[1] * kLn2, s9[2] * kLn2, s9[3] * kLn2);
+      const float qa2 = 2.0f * L.p1[e].z, qb = L.p1[e].w, qc2 = 2.0f * L.p2[e].x;
+      const float d_offx = -qa2 * s9[0], d_offy = -fmaf(qa2 * qb, s9[0], qc2 * s9[1]);
+      ws.partials[(size_t)slot * 3 + 0] = make_float4(d_offx * kLn2, d_offy * kLn2, s9[2] * kLn2, qa2 * s9[3] * kLn2);
       ws.partials[(size_t)slot * 3 + 1] = make_float4(s9[4] * kLn2, s9[5], s9[6], s9[7]);
       ws.partials[(size_t)slot * 3 + 2] = make_float4(s9[8], 0.0f, 0.0f, 0.0f);
     }
