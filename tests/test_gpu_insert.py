@@ -67,8 +67,9 @@ def _check(cams, gts, rds, depths, sigma=1.0, tau=0.2):
     common = np.intersect1d(pix, ref_pix)
     gi = np.searchsorted(pix, common)
     ri = np.searchsorted(ref_pix, common)
-    assert np.abs(scale[gi] - ref_scale[ri]).max() <= 1e-5 * np.abs(ref_scale[ri]).max()
-    assert np.abs(mean[gi] - ref_mean[ri]).max() <= 1e-5 * max(1.0, np.abs(ref_mean[ri]).max())
+    if len(common):
+        assert np.abs(scale[gi] - ref_scale[ri]).max() <= 1e-5 * np.abs(ref_scale[ri]).max()
+        assert np.abs(mean[gi] - ref_mean[ri]).max() <= 1e-5 * max(1.0, np.abs(ref_mean[ri]).max())
     log(f"{len(cams)} views: {n} inserting pixels (oracle {len(ref_pix)}, {len(amb)} ambiguous)")
     return n
 
@@ -99,6 +100,15 @@ def test_insert_capacity_overflow_and_determinism():
     for key in ("p_gt", "p_render", "pix", "scale", "mean", "count"):
         assert torch.equal(again[key][:n] if key in ("pix", "scale", "mean") else again[key],
                            full[key][:n] if key in ("pix", "scale", "mean") else full[key]), key
+
+
+def test_insert_nothing_to_insert_on_tiny_and_ragged_views():
+    """Render equal to the ground truth (P_a = 0 everywhere) on views smaller
+    than a tile and than the filter: P maps still match, the list is empty."""
+    sizes = [(1, 1), (3, 2), (70, 17)]
+    cams = _cams(sizes, 97)
+    gts, _, depths = make_insert_inputs(sizes, 97)
+    assert _check(cams, gts, gts, depths) == 0
 
 
 def test_insert_rig_views():

@@ -114,3 +114,28 @@ def test_merge_rig_views_with_the_scene():
         log(f"view {view}: {len(o['pix'])} samples")
         total += _compare(res, ref, scene.n, len(o["pix"]))
     assert total > 100
+
+
+def test_merge_without_samples():
+    """An empty sample list: every existing Gaussian is kept with its own DC
+    colour and the spare sample entries are untouched."""
+    rng = np.random.default_rng(62)
+    cams = [camera(f=50.0, w=40, h=30)]
+    rast = Rasterizer(cams, 1, 0)
+    N = 200
+    mean = np.stack([rng.uniform(-1, 1, N), rng.uniform(-1, 1, N), rng.uniform(2, 6, N)]).astype(np.float32)
+    ls = rng.normal(-3.0, 0.5, (3, N)).astype(np.float32)
+    sh = rng.normal(0, 1, (1, 3, N)).astype(np.float32)
+    gt = rng.uniform(0, 1, 3 * rast.total_px).astype(np.float32)
+    host, dev = _samples_for(rast, cams, 0, np.zeros(0, np.int64), np.zeros((0, 3), np.float32), gt)
+    dev["p_gt"] = torch.full((rast.total_px,), 0.5, dtype=torch.float32, device="cuda")
+    ex = {k_: torch.from_numpy(np.ascontiguousarray(v_)).cuda() for k_, v_ in
+          (("mean", mean), ("log_scale", ls), ("sh", sh))}
+    res = rast.merge(ex, 0, torch.from_numpy(gt).cuda(), dev, tau_d=1.0)
+    torch.cuda.synchronize()
+    ref = merge(mean, ls, sh[0], cams[0], host, np.full((30, 40), 0.5), tau_d=1.0)
+    assert ref["keep"].all()
+    assert res["keep"][:N].cpu().numpy().astype(bool).all()
+    colour = res["colour"][:, :N].cpu().numpy().astype(np.float64).T
+    assert np.abs(colour - ref["colour"]).max() <= 1e-6
+    assert not res["keep_new"].any()
