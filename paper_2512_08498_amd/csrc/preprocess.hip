@@ -28,37 +28,138 @@ __device__ __forceinline__ uint32_t rect_area(const Proj &P, int ts_shift) {
   return w * h;
 }
 
+// Screen for the counting pass: false only if (view c, Gaussian) is certainly
+// invisible under the binning rules of spec.hpp.  The camera-space depth is
+// computed exactly as there (the same operations in the same order), so
+// the near-plane test is the same decision.
+// The pixel box is bounded from above with fast reciprocals: the half
+// extent hx = sqrt(K (|t0 M|^2 + 0.3)) with |t0 M| <= |t0| s_max and
+// |t0| <= |j00| |R_0| + |j02| |R_2| (rows of the view rotation, bounded by
+// their L1 norms), so hx_b >= hx after a 1e-4 relative inflation that covers
+// every rounding involved (hardware reciprocal and square root included);
+// the box misses the image only if u + hx < 0.5 or u - hx > w - 0.5, tested
+// with a margin of 1 px plus 2e-5 of the magnitudes for the rounding of u.
+// s2 is the square of the largest scale, inflated the same way.  NaN keeps
+// the pair.
+__device__ __forceinline__ bool may_be_visible(const float m3[3], float s2, const Cam &c) {
+  float xc, yc, zc;
+  {
+#pragma clang fp contract(off)
+    xc = ((c.R[0] * m3[0] + c.R[1] * m3[1]) + c.R[2] * m3[2]) + c.t[0];
+    yc = ((c.R[3] * m3[0] + c.R[4] * m3[1]) + c.R[5] * m3[2]) + c.t[1];
+    zc = ((c.R[6] * m3[0] + c.R[7] * m3[1]) + c.R[8] * m3[2]) + c.t[2];
+  }
+  if (!(zc > kNearZ)) return false;
+  const float rz = __builtin_amdgcn_rcpf(zc);
+  const float xz = xc * rz, yz = yc * rz;
+  const float u = fmaf(c.fx, xz, c.cx), v = fmaf(c.fy, yz, c.cy);
+  const float wf = (float)c.w, hf = (float)c.h;
+  // |xt| of the guard clamp: min(|x/z|, lim) for lim >= 0, |lim| otherwise
+  const float lim_x = kClampFov * fmaxf(c.cx, wf - c.cx) * __builtin_amdgcn_rcpf(c.fx);
+  const float lim_y = kClampFov * fmaxf(c.cy, hf - c.cy) * __builtin_amdgcn_rcpf(c.fy);
+  const float axt = lim_x >= 0.0f ? fminf(fabsf(xz), lim_x) : -lim_x;
+  const float ayt = lim_y >= 0.0f ? fminf(fabsf(yz), lim_y) : -lim_y;
+  // row norms of the view rotation, bounded by their L1 norms
+  const float n0 = (fabsf(c.R[0]) + fabsf(c.R[1])) + fabsf(c.R[2]);
+  const float n1 = (fabsf(c.R[3]) + fabsf(c.R[4])) + fabsf(c.R[5]);
+  const float n2 = (fabsf(c.R[6]) + fabsf(c.R[7])) + fabsf(c.R[8]);
+  const float tx = fabsf(c.fx) * rz * fmaf(axt, n2, n0);
+  const float ty = fabsf(c.fy) * rz * fmaf(ayt, n2, n1);
+  const float hx = 1.0001f * __builtin_amdgcn_sqrtf(kSupportK * fmaf(tx * tx, s2, kDilation));
+  const float hy = 1.0001f * __builtin_amdgcn_sqrtf(kSupportK * fmaf(ty * ty, s2, kDilation));
+  const float ex = fmaf(2e-5f, (fabsf(c.fx * xz) + fabsf(c.cx)) + hx, 1.0f);
+  const float ey = fmaf(2e-5f, (fabsf(c.fy * yz) + fabsf(c.cy)) + hy, 1.0f);
+  const bool out = (u + hx < 0.5f - ex) || (u - hx > wf - 0.5f + ex) || (v + hy < 0.5f - ey) ||
+                   (v - hy > hf - 0.5f + ey);
+  return !out;
+}
+
+constexpr int kScreenViews = 16;  // views screened per round of the counting pass
+
+// Counting pass: per Gaussian, its visible views (a bit mask), record count
+// and (record, tile) pair count, block-scanned.  Each wave screens its 64
+// Gaussians against 16 views at a time, queues the (Gaussian, view) pairs
+// that may be visible in LDS and runs the exact binning rules on the queue
+// 64 at a time, so the rules' cost follows the visible pairs rather than
+// every lane's every view.  The results are integer LDS atomics on the
+// owning Gaussian's counters, the same whatever the order.
 // Also clears the n_zero words at `zero` (the forward's counters and tile
 // ranges, which no kernel before the scan reads), saving a launch.
 __global__ __launch_bounds__(kPreBlock) void k_pre_count(GaussPtrs gp, const Cam *__restrict__ cams,
                                                          Ws ws, Sizes sz, int ts_shift, uint32_t *__restrict__ zero,
                                                          uint64_t n_zero) {
-  __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
-  const int64_t g = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  constexpr int NW = kPreBlock / kWave;
+  __shared__ uint32_t s_scan[NW * 2];
+  __shared__ float s_par[10][kPreBlock];                   // mean, log-scale, quaternion of each Gaussian
+  __shared__ uint32_t s_cnt[3][kPreBlock];                 // records, pairs, visible-view bits of the round
+  __shared__ uint16_t s_q[NW][kWave * kScreenViews];       // queued (lane, view) pairs of each wave
+  const int t = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int64_t g = (int64_t)blockIdx.x * kPreBlock + t;
   for (uint64_t i = (uint64_t)g; i < n_zero; i += (uint64_t)gridDim.x * kPreBlock) zero[i] = 0u;
-  uint32_t recs = 0, pairs = 0;
-  if (g < sz.n) {
-    float m3[3], l3[3], q4[4];
-    load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
-    uint64_t word = 0;
-    for (int v = 0; v < sz.n_views; ++v) {
-      const Cam c = load_cam(cams, v);
-      Proj P;
-      project_spec(m3, l3, q4, c, P);
-      if (P.visible) {
-        recs += 1;
-        pairs += rect_area(P, ts_shift);
-        word |= uint64_t(1) << (v & 63);
-      }
-      if ((v & 63) == 63 || v == sz.n_views - 1) {
-        ws.vis_mask[(int64_t)(v >> 6) * sz.n + g] = word;
-        word = 0;
+  const bool live = g < sz.n;
+  float m3[3] = {0.f, 0.f, 0.f}, l3[3] = {0.f, 0.f, 0.f}, q4[4] = {0.f, 0.f, 0.f, 0.f};
+  if (live) load_gaussian(gp.mean, gp.log_scale, gp.quat, sz.n, g, m3, l3, q4);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s_par[k][t] = m3[k];
+    s_par[3 + k][t] = l3[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s_par[6 + k][t] = q4[k];
+  s_cnt[0][t] = s_cnt[1][t] = s_cnt[2][t] = 0u;
+  const float smax = expf(fmaxf(fmaxf(l3[0], l3[1]), l3[2]));
+  const float s2 = 1.0001f * (smax * smax);
+  uint64_t word = 0;
+  for (int v0 = 0; v0 < sz.n_views; v0 += kScreenViews) {
+    const int nv = min(kScreenViews, sz.n_views - v0);
+    uint32_t m = 0;
+    if (live)
+      for (int j = 0; j < nv; ++j)
+        if (may_be_visible(m3, s2, load_cam(cams, v0 + j))) m |= 1u << j;
+    // queue this lane's candidate views after those of the lanes below it
+    const uint32_t c = (uint32_t)__popc(m);
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t total = (uint32_t)__shfl(incl, kWave - 1, kWave);
+    uint32_t pos = incl - c;
+    for (uint32_t mm = m; mm; mm &= mm - 1) s_q[wv][pos++] = (uint16_t)((lane << 4) | (__ffs(mm) - 1));
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's queue is written
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t base = 0; base < total; base += kWave) {
+      const uint32_t e = base + (uint32_t)lane;
+      if (e < total) {
+        const uint32_t q = s_q[wv][e];
+        const int o = wv * kWave + (int)(q >> 4), j = (int)(q & 15u);
+        float pm[3], pl[3], pq[4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          pm[k] = s_par[k][o];
+          pl[k] = s_par[3 + k][o];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pq[k] = s_par[6 + k][o];
+        Proj P;
+        project_spec(pm, pl, pq, load_cam(cams, v0 + j), P);
+        if (P.visible) {
+          atomicAdd(&s_cnt[0][o], 1u);
+          atomicAdd(&s_cnt[1][o], rect_area(P, ts_shift));
+          atomicOr(&s_cnt[2][o], 1u << j);
+        }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // the wave's counter updates are done
+    __builtin_amdgcn_wave_barrier();
+    word |= (uint64_t)s_cnt[2][t] << (v0 & 63);
+    s_cnt[2][t] = 0u;
+    const int v_end = v0 + nv;
+    if ((v_end & 63) == 0 || v_end == sz.n_views) {
+      if (live) ws.vis_mask[(int64_t)(v0 >> 6) * sz.n + g] = word;
+      word = 0;
+    }
   }
+  const uint32_t recs = s_cnt[0][t], pairs = s_cnt[1][t];
   uint32_t tr, tp;
   block_excl_scan<kPreBlock>(recs, s_scan, tr);
-  block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
+  block_excl_scan<kPreBlock>(pairs, s_scan + NW, tp);
   if (threadIdx.x == 0) ws.block_sums[blockIdx.x] = make_uint2(tr, tp);
 }
 
