@@ -124,6 +124,45 @@ def test_needles_forward_and_backward(ts, long_list):
     _check_backward(scene, cams, targets, ts, long_list=long_list)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_binning_extreme_scenes(seed):
+    """Tile lists bit for bit on scenes far from the workloads: coordinates up
+    to 1e4, scales from 1e-3 to 1e2 of the scene, rotated cameras with
+    principal points outside the image and unequal focal lengths (the
+    visibility of every (view, Gaussian) pair decides the lists)."""
+    import math
+
+    from tiny_scenes import camera
+    from workloads.generators import Scene
+
+    rng = np.random.default_rng(700 + seed)
+    scale = 10.0 ** rng.uniform(-1, 4)
+    n = 6000
+    mean = rng.standard_normal((3, n)) * scale
+    mean[2] += scale * rng.uniform(0, 2)
+    q = rng.standard_normal((4, n))
+    scene = Scene(mean=mean.astype(np.float32),
+                  log_scale=(rng.normal(math.log(scale) - 5, 1.5, (3, n))).astype(np.float32),
+                  quat=q.astype(np.float32), opacity_logit=rng.normal(0, 1, n).astype(np.float32),
+                  sh=rng.normal(0, 0.5, (1, 3, n)).astype(np.float32), sh_degree=0)
+    cams = []
+    for _ in range(3):
+        a, b = rng.uniform(-3, 3, 2)
+        R = np.array([[math.cos(a), 0, math.sin(a)], [0, 1, 0], [-math.sin(a), 0, math.cos(a)]]) @ \
+            np.array([[1, 0, 0], [0, math.cos(b), -math.sin(b)], [0, math.sin(b), math.cos(b)]])
+        w, h = int(rng.integers(40, 200)), int(rng.integers(30, 150))
+        f = float(rng.uniform(0.3, 3.0) * w)
+        cams.append(camera(f=f, w=w, h=h, cx=float(rng.uniform(-0.2, 1.2) * w), cy=float(rng.uniform(-0.2, 1.2) * h),
+                           R=R, t=rng.standard_normal(3) * scale, fy=f * float(rng.uniform(0.7, 1.4))))
+    log(f"extreme binning seed={seed} scale={scale:.3g}")
+    rast, params, out = render_gpu(scene, cams, ts=16)
+    keys, vals, csr = rast.debug_binning()
+    okeys, ovals, ocsr = tile_lists(scene, cams, 16)
+    log(f"  {len(okeys)} pairs")
+    assert len(keys) == len(okeys)
+    assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals) and np.array_equal(csr, ocsr)
+
+
 def _oracle_evaluations(scene, cams, oracle):
     """Bounds (lo, hi) on the backward's evaluation count from the oracle:
     per pixel, the Gaussians whose pixel box holds it, up to and including
