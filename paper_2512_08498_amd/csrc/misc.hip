@@ -45,18 +45,6 @@ __global__ __launch_bounds__(256) void k_l1(const float *__restrict__ img, const
   if (threadIdx.x == 0) partials[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
-// Thread t adds blocks t, t + 256, ... in order; then a fixed-shape tree.
-__global__ __launch_bounds__(256) void k_l1_final(const float *__restrict__ partials, uint32_t nb, int64_t n,
-                                                  float *__restrict__ loss) {
-  __shared__ double s_d[4];
-  double s = 0.0;
-  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) s += (double)partials[b];
-  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
-  if (lane_id() == 0) s_d[wave_id()] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) *loss = (float)(((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)n);
-}
-
 // The mean from many partials: 1024 threads, thread t adding partials
 // t, t + 1024, ... in order (in double), then the 16 waves' sums in order.
 __global__ __launch_bounds__(1024) void k_l1_sum(const float *__restrict__ partials, uint32_t nb, int64_t n,
@@ -75,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_l1_sum(const float *__restrict__ parti
   }
 }
 
-void launch_l1_final(const float *partials, uint32_t nb, int64_t n, float *loss, hipStream_t st) {
+void launch_l1_sum(const float *partials, uint32_t nb, int64_t n, float *loss, hipStream_t st) {
   k_l1_sum<<<1, 1024, 0, st>>>(partials, nb, n, loss);
 }
 
@@ -86,7 +74,7 @@ void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float
   const int64_t work = vec ? (n + 3) / 4 : n;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, kLossBlocks));
   k_l1<<<(unsigned)blocks, 256, 0, st>>>(img, tgt, n, dl, partials, vec ? 1 : 0);
-  k_l1_final<<<1, 256, 0, st>>>(partials, (uint32_t)blocks, n, loss);
+  launch_l1_sum(partials, (uint32_t)blocks, n, loss, st);
 }
 
 // One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian;

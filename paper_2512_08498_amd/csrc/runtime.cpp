@@ -386,7 +386,7 @@ gsr_status gsr_render_forward_l1(gsr_ctx *c, const gsr_gaussians *g, const gsr_c
   hipStream_t s = static_cast<hipStream_t>(stream);
   {
     StageTimer tm(c, GSR_STAGE_LOSS, s);
-    launch_l1_final(part, raster_fwd_grid(c->sz), n, loss_out, s);
+    launch_l1_sum(part, raster_fwd_grid(c->sz), n, loss_out, s);
   }
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;
