@@ -34,6 +34,13 @@ def camera_rows(cams) -> np.ndarray:
     return rows
 
 
+def _check_flat(name, t: torch.Tensor, numel, device):
+    """A contiguous float32 tensor of numel elements on device, any shape."""
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device or t.numel() != numel:
+        raise ValueError(f"{name}: expected contiguous float32 with {numel} elements on {device}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device} (contiguous={t.is_contiguous()})")
+
+
 def _check_param(name, t: torch.Tensor, shape, device):
     if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device or tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name}: expected contiguous float32 {tuple(shape)} on {device}, got "
@@ -220,6 +227,8 @@ class Rasterizer:
         g = self._gaussians(params)
         if grads is None:
             grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+        for k in PARAM_NAMES:
+            _check_param(f"grads[{k}]", grads[k], tuple(params[k].shape), self.device)
         if cam_grads is True:
             cam_grads = torch.empty(self.views, 12, dtype=torch.float32, device=self.device)
         if cam_grads is not None:
@@ -227,6 +236,7 @@ class Rasterizer:
         gr = L.Grads(*(grads[k].data_ptr() for k in PARAM_NAMES), self._cam_grad_ptr(cam_grads))
         cams = cams_dev if cams_dev is not None else self.cams_dev
         dl = dL_dimage.contiguous()
+        _check_flat("dL_dimage", dl, 3 * self.total_px, self.device)
         self._check(self.lib.gsr_render_backward(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
                                                  self.ws_bytes, C.byref(self._fwd_struct(fwd)), _vp(dl),
                                                  C.byref(gr), 1 if accumulate else 0, self.stream()))
@@ -238,6 +248,10 @@ class Rasterizer:
         the views' pose gradients."""
         g = self._gaussians(params)
         cams = cams_dev if cams_dev is not None else self.cams_dev
+        _check_flat("dL_dimage", dL_dimage, 3 * self.total_px, self.device)
+        if grads_out is not None:
+            for k in PARAM_NAMES:
+                _check_param(f"grads_out[{k}]", grads_out[k], tuple(params[k].shape), self.device)
         go = None
         if grads_out is not None or cam_grads is not None:
             ptrs = [grads_out[k].data_ptr() for k in PARAM_NAMES] if grads_out is not None else [None] * 5
@@ -249,8 +263,13 @@ class Rasterizer:
             self.stream()))
 
     def l1_loss(self, image, target, loss_out=None, dl_out=None):
+        n = image.numel()
+        _check_flat("image", image, n, self.device)
+        _check_flat("target", target, n, self.device)
         loss_out = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=self.device)
         dl_out = dl_out if dl_out is not None else torch.empty_like(image)
+        _check_flat("loss_out", loss_out, 1, self.device)
+        _check_flat("dl_out", dl_out, n, self.device)
         self._check(self.lib.gsr_l1_loss(self.ctx, _vp(image), _vp(target), image.numel(), _vp(loss_out),
                                          _vp(dl_out), self.stream()))
         return loss_out, dl_out

@@ -49,3 +49,22 @@ def test_camera_struct_layout_matches_rows():
     for c, a in zip(cams, arr):
         assert a.width == c.width and a.height == c.height
         assert np.allclose(list(a.R), np.asarray(c.R).reshape(-1)) and a.fx == np.float32(c.fx)
+
+
+def test_binding_rejects_tensors_the_entry_points_would_misread():
+    """The binding checks dtype, device, contiguity and size before handing a
+    pointer to the C ABI, which cannot check them itself."""
+    import torch
+
+    from paper_2512_08498_amd.rasterizer import _check_flat, _check_param
+
+    cpu = torch.device("cpu")
+    ok = torch.zeros(12, dtype=torch.float32)
+    _check_flat("x", ok, 12, cpu)
+    _check_flat("x", ok.view(3, 4), 12, cpu)
+    _check_param("x", ok.view(3, 4), (3, 4), cpu)
+    for bad in (ok.double(), ok[:11], ok.view(3, 4).t(), torch.zeros(13)):
+        with pytest.raises(ValueError):
+            _check_flat("x", bad, 12, cpu)
+    with pytest.raises(ValueError):
+        _check_param("x", ok.view(4, 3), (3, 4), cpu)
