@@ -374,6 +374,13 @@ class Rasterizer:
             _check_param(name, existing[name], shape, self.device)
         _check_param("gt", gt, (3 * self.total_px,), self.device)
         cap = ins["pix"].numel()
+        for name, dtype, shape in (("pix", torch.int32, (cap,)), ("count", torch.int32, (1,)),
+                                   ("mean", torch.float32, (cap, 3)), ("scale", torch.float32, (cap,)),
+                                   ("p_gt", torch.float32, (self.total_px,))):
+            t = ins[name]
+            if t.dtype != dtype or not t.is_contiguous() or t.device != self.device or tuple(t.shape) != shape:
+                raise ValueError(f"ins[{name}]: expected contiguous {dtype} {shape} on {self.device}, got "
+                                 f"{t.dtype} {tuple(t.shape)} on {t.device}")
         nb = C.c_size_t()
         self._check(self.lib.gsr_merge_workspace(self.ctx, n, C.byref(nb)))
         ws = getattr(self, "_merge_ws", None)
