@@ -13,6 +13,9 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
                 from HIP events recorded around it on the library's stream
                 during an eager pass of the same steps
   cpu_baseline  the FP64 CPU oracle timed on a bounded pixel sample
+  step_ms_spread  p10 / median / p90 of 30 single replays (HIP events)
+  hbm_copy_gbs  achievable HBM bandwidth (the library's streaming copy of
+                1 GiB), and the step's algorithmic bytes as a fraction of it
   per_view      the same step issued as plain per-view launches (no batching,
                 no graph), for comparison
   pose          the same step with each view's camera-pose gradient and its
@@ -185,7 +188,7 @@ def main():
 
     import torch
 
-    from paper_2512_08498_amd import FusedAdam, Frequency, Rasterizer
+    from paper_2512_08498_amd import FusedAdam, Frequency, Rasterizer, device_copy
     from workloads import RIG_LAYOUT, config_names, make_config, make_insert_inputs, make_target
 
     dev = torch.device("cuda", 0)
@@ -266,6 +269,34 @@ def main():
     total_px = rast.total_px
     rec, pairs, tiles = rast.required_capacity()
     log(f"{it_s:.2f} it/s, {ms:.3f} ms/step, loss {loss.item():.5f}")
+
+    # spread of single steps: HIP events around each of 30 more replays, on
+    # the stream the replays run on
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(30)]
+    for a, b in evs:
+        a.record()
+        run()
+        b.record()
+    torch.cuda.synchronize(dev)
+    t_each = np.array([a.elapsed_time(b) for a, b in evs])
+    spread = {"replays": len(t_each), "p10": float(np.percentile(t_each, 10)), "median": float(np.median(t_each)),
+              "p90": float(np.percentile(t_each, 90))}
+    log(f"single steps: median {spread['median']:.3f} ms (p10 {spread['p10']:.3f}, p90 {spread['p90']:.3f})")
+
+    # achievable HBM bandwidth: the library's streaming copy of 1 GiB, read +
+    # write bytes
+    src = torch.ones(2**28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    device_copy(dst, src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        device_copy(dst, src)
+    c1.record()
+    torch.cuda.synchronize(dev)
+    copy_gbs = 2 * src.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    log(f"streaming copy: {copy_gbs:.0f} GB/s ({copy_gbs / HBM_PEAK_GBS:.1%} of the 8 TB/s peak)")
 
     # per-stage durations from HIP events around each stage (eager steps)
     rast.profile(True)
@@ -499,6 +530,9 @@ def main():
         "stages": stages,
         "step_hbm_bytes": total_b,
         "step_hbm_frac": total_b / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "step_ms_spread": spread,
+        "hbm_copy_gbs": copy_gbs,
+        "step_hbm_frac_of_copy": total_b / (ms * 1e-3) / (copy_gbs * 1e9),
         "combined_roofline_frac": ideal_s / (ms * 1e-3),
         "roofline": roofline,
         "cpu_baseline": cpu,

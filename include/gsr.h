@@ -225,6 +225,13 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, void *workspace, uint64_t *keys, uint
 gsr_status gsr_count_evaluations(gsr_ctx *ctx, void *workspace, const gsr_fwd_out *fwd, uint64_t *evals,
                                  void *stream);
 
+/* Measurement: copy `bytes` (a multiple of 16) from src to dst (DEVICE,
+ * 16-byte aligned, not overlapping) with the library's streaming copy
+ * kernel, to time the achievable HBM bandwidth against which the kernels'
+ * bytes are reported.  Enqueues only; GSR_ERR_INVALID_ARG on a misaligned or
+ * NULL pointer or a size that is not a multiple of 16.  Needs no context.   */
+gsr_status gsr_copy_bytes(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Synchronise `stream`, then report GSR_ERR_CAPACITY if the last forward ran
  * out of record or pair capacity, else GSR_OK.                              */
 gsr_status gsr_check(gsr_ctx *ctx, void *workspace, void *stream);
@@ -450,6 +457,9 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
                         const gsr_plan_options *opt, int32_t repeats, const char *cache_path, gsr_tuning *best,
                         void *stream);
 
+/* Message of the context's last failure; with ctx NULL, that of this
+ * thread's last failed call that takes no context (gsr_copy_bytes).  The
+ * string is owned by the library and valid until the next call.            */
 const char *gsr_last_error(const gsr_ctx *ctx);
 
 #ifdef __cplusplus

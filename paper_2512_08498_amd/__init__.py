@@ -12,5 +12,6 @@ from .rasterizer import (  # noqa: F401
     RasterizeFn,
     Rasterizer,
     camera_rows,
+    device_copy,
     rasterize,
 )

@@ -93,6 +93,7 @@ _SIGS = {
                                  C.POINTER(AdamConfig), P, C.POINTER(Grads), P],
     "gsr_debug_binning": [P, P, P, P, P, P],
     "gsr_count_evaluations": [P, P, C.POINTER(FwdOut), P, P],
+    "gsr_copy_bytes": [P, P, C.c_size_t, P],
     "gsr_check": [P, P, P],
     "gsr_required_capacity": [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P],
     "gsr_set_tuning": [P, C.POINTER(Tuning)],

@@ -66,6 +66,7 @@ void launch_tile_csr(const Ws &ws, const Sizes &sz, uint32_t *csr, hipStream_t s
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
                        uint32_t *last_pos, uint32_t *n_contrib, const LossArgs &loss, hipStream_t st);
 void launch_l1_sum(const float *partials, uint32_t nb, int64_t n, float *loss, hipStream_t st);
+void launch_copy16(void *dst, const void *src, uint64_t n16, hipStream_t st);
 uint32_t raster_fwd_grid(const Sizes &sz);
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st);

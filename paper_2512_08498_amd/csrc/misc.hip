@@ -77,6 +77,34 @@ void launch_l1(const float *img, const float *tgt, int64_t n, float *loss, float
   launch_l1_sum(partials, (uint32_t)blocks, n, loss, st);
 }
 
+// Streaming copy for the bandwidth measurement: each workgroup moves one
+// contiguous 16 KB chunk, each thread four 16-byte words (all loads issued
+// before the stores), with non-temporal accesses so the copy does not
+// occupy the caches.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint64_t kCopyChunk = 256 * 4;  // 16-byte words per workgroup
+
+__global__ __launch_bounds__(256) void k_copy16(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src, uint64_t n) {
+  const uint64_t base = (uint64_t)blockIdx.x * kCopyChunk + threadIdx.x;
+  u32x4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t i = base + 256u * k;
+    if (i < n) v[k] = __builtin_nontemporal_load(src + i);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t i = base + 256u * k;
+    if (i < n) __builtin_nontemporal_store(v[k], dst + i);
+  }
+}
+
+void launch_copy16(void *dst, const void *src, uint64_t n16, hipStream_t st) {
+  if (n16 == 0) return;
+  const uint64_t blocks = (n16 + kCopyChunk - 1) / kCopyChunk;
+  k_copy16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<u32x4 *>(dst), static_cast<const u32x4 *>(src), n16);
+}
+
 // One workgroup per tile: keys = tile << 32 | depth bits, values = Gaussian;
 // the CSR offsets are the exclusive scan of the list lengths.
 __global__ __launch_bounds__(256) void k_debug_binning(Ws ws, Sizes sz, uint64_t *__restrict__ keys,

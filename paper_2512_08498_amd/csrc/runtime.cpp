@@ -546,6 +546,24 @@ gsr_status gsr_count_evaluations(gsr_ctx *c, void *ws_base, const gsr_fwd_out *f
   return GSR_OK;
 }
 
+// Message of the last failed call that has no context (gsr_copy_bytes).
+static thread_local std::string g_err_no_ctx = "NULL context";
+
+gsr_status gsr_copy_bytes(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 != 0 ||
+      bytes / 16 > (uint64_t(1) << 40)) {
+    g_err_no_ctx = "gsr_copy_bytes: pointers must be non-NULL and 16-byte aligned, the size a multiple of 16 (< 16 TiB)";
+    return GSR_ERR_INVALID_ARG;
+  }
+  launch_copy16(dst, src, bytes / 16, static_cast<hipStream_t>(stream));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_err_no_ctx = std::string("gsr_copy_bytes: ") + hipGetErrorString(e);
+    return GSR_ERR_HIP;
+  }
+  return GSR_OK;
+}
+
 static gsr_status read_scalars(gsr_ctx *c, void *ws_base, void *stream, uint32_t out[kNumScalars]) {
   if (!c) return GSR_ERR_INVALID_ARG;
   if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
@@ -619,7 +637,7 @@ gsr_status gsr_profile_read(gsr_ctx *c, double *ms, int64_t *calls, int32_t rese
   return GSR_OK;
 }
 
-const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+const char *gsr_last_error(const gsr_ctx *c) { return c ? c->err.c_str() : g_err_no_ctx.c_str(); }
 
 gsr_status gsr_freq_plan(gsr_ctx *c, const int32_t *widths, const int32_t *heights, int32_t n_images,
                          size_t *workspace_bytes) {

@@ -41,6 +41,18 @@ def _check_flat(name, t: torch.Tensor, numel, device):
                          f"{t.dtype} {tuple(t.shape)} on {t.device} (contiguous={t.is_contiguous()})")
 
 
+def device_copy(dst: torch.Tensor, src: torch.Tensor):
+    """Copy src into dst (contiguous device tensors of the same byte size, a
+    multiple of 16) with the library's streaming copy kernel, on the current
+    stream: the reference for achievable HBM bandwidth."""
+    nbytes = src.numel() * src.element_size()
+    if (not src.is_contiguous() or not dst.is_contiguous() or src.device.type != "cuda" or dst.device != src.device
+            or dst.numel() * dst.element_size() != nbytes):
+        raise ValueError("device_copy: contiguous device tensors of the same byte size expected")
+    lib = L.load()
+    L.check(None, lib.gsr_copy_bytes(_vp(dst), _vp(src), nbytes, torch.cuda.current_stream(src.device).cuda_stream))
+
+
 def _check_param(name, t: torch.Tensor, shape, device):
     if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device or tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name}: expected contiguous float32 {tuple(shape)} on {device}, got "

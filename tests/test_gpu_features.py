@@ -328,3 +328,19 @@ def test_forward_with_fused_l1_loss(ts):
     ref_loss, _ = l1_loss([r["image"] for r in ref], targets)
     log(f"ts {ts}: fused {loss_b.item():.8f}, separate {loss_a.item():.8f}, oracle {ref_loss:.8f}")
     assert abs(loss_b.item() - ref_loss) <= 1e-5 * ref_loss
+
+
+def test_streaming_copy():
+    """The bandwidth reference copy moves every byte, tails included, and
+    rejects sizes that are not a multiple of 16 bytes."""
+    from paper_2512_08498_amd import device_copy
+    from paper_2512_08498_amd._lib import GsrError
+
+    for n in (4, 1028, 3 * 2**20 + 12):
+        src = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda")
+        dst = torch.zeros_like(src)
+        device_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    with pytest.raises(GsrError):
+        device_copy(torch.zeros(3, dtype=torch.int32, device="cuda"), torch.zeros(3, dtype=torch.int32, device="cuda"))
