@@ -148,9 +148,12 @@ constexpr int kColMaxElems = 3 * 2560;
 // exp(-2 pi i k r / (Ns P)) (k = j mod Ns; table entry k r N / (Ns P)),
 // transforms, and writes (j / Ns) Ns P + k + q Ns.  All butterflies of the
 // thread are loaded and transformed before the barrier, then stored, so one
-// LDS buffer suffices.
+// LDS buffer suffices.  Not inlined: each radix then gets its own register
+// allocation (71 to 113 VGPRs), where inlining all five into the stage loop
+// made the kernels allocate for their union (241 VGPRs, two waves per SIMD
+// instead of three).
 template <int P, int T, int MAXE>
-__device__ __forceinline__ void fft_stage(float2 *buf, int N, int cnt, int Ns, const float2 *tw) {
+__device__ __attribute__((noinline)) void fft_stage(float2 *buf, int N, int cnt, int Ns, const float2 *tw) {
   constexpr int kMaxB = (MAXE / P + T - 1) / T;
   const int m = N / P;
   const int total = cnt * m;
