@@ -82,12 +82,92 @@ struct Roots<7> {
   }
 };
 
+// Composite radices P = A B, done in registers as B DFTs of size A, the
+// twiddles exp(-2 pi i a b / P), then A DFTs of size B (Cooley-Tukey with
+// n = B n1 + n2, k = k1 + A k2), so one Stockham stage covers two factors.
+template <int P>
+struct Split {
+  static constexpr int A = 1, B = P;
+};
+template <> struct Split<8> { static constexpr int A = 4, B = 2; };
+template <> struct Split<9> { static constexpr int A = 3, B = 3; };
+template <> struct Split<15> { static constexpr int A = 3, B = 5; };
+template <> struct Split<16> { static constexpr int A = 4, B = 4; };
+template <> struct Split<20> { static constexpr int A = 4, B = 5; };
+template <> struct Split<25> { static constexpr int A = 5, B = 5; };
+template <> struct Split<27> { static constexpr int A = 3, B = 9; };
+
+// cos and sin at compile time: Taylor series in double on |x| <= pi (30
+// terms, far below float resolution).
+constexpr double ct_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 30; ++k) {
+    t *= -x * x / (double)((2 * k) * (2 * k + 1));
+    s += t;
+  }
+  return s;
+}
+constexpr double ct_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    t *= -x * x / (double)((2 * k - 1) * (2 * k));
+    s += t;
+  }
+  return s;
+}
+
+// cos and sin of 2 pi m / P, m = 0 .. P - 1.
+template <int P>
+struct TwiddleTable {
+  float c[P], s[P];
+  constexpr TwiddleTable() : c(), s() {
+    constexpr double kPi = 3.14159265358979323846;
+    for (int m = 0; m < P; ++m) {
+      double x = 2.0 * kPi * m / P;
+      if (x > kPi) x -= 2.0 * kPi;
+      c[m] = (float)ct_cos(x);
+      s[m] = (float)ct_sin(x);
+    }
+  }
+};
+
+template <int P>
+__device__ __forceinline__ void dft(float2 *v);
+
+template <int P>
+__device__ __forceinline__ void dft_composite(float2 *v) {
+  constexpr int A = Split<P>::A, B = Split<P>::B;
+  constexpr TwiddleTable<P> tw{};
+  float2 t[P];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    float2 u[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) u[a] = v[b + B * a];
+    dft<A>(u);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const int m = (a * b) % P;  // u exp(-2 pi i m / P) = u (c - i s)
+      t[a * B + b] = m == 0 ? u[a]
+                            : make_float2(u[a].x * tw.c[m] + u[a].y * tw.s[m], u[a].y * tw.c[m] - u[a].x * tw.s[m]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < A; ++a) dft<B>(t + a * B);
+#pragma unroll
+  for (int a = 0; a < A; ++a)
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[a + A * b] = t[a * B + b];
+}
+
 // In-register radix-P DFT with the forward sign.  Radices 3 and 5 use the
 // symmetric forms: with s_k = x_k + x_{P-k} and d_k = x_k - x_{P-k},
 // X_q = x_0 + sum_k cos(2 pi k q / P) s_k - i sum_k sin(2 pi k q / P) d_k.
 template <int P>
 __device__ __forceinline__ void dft(float2 *v) {
-  if constexpr (P == 3) {
+  if constexpr (Split<P>::A > 1) {
+    dft_composite<P>(v);
+  } else if constexpr (P == 3) {
     constexpr float s1 = 0.86602540378443865f;  // sin(2 pi / 3)
     const float2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
     const float2 a = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
@@ -202,6 +282,13 @@ __device__ __forceinline__ void fft_lds(float2 *buf, int N, int cnt, const float
   int Ns = 1;
   for (int s = 0; s < nfac; ++s) {
     switch (fac[s]) {
+      case 27: fft_stage<27, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 25: fft_stage<25, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 20: fft_stage<20, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 16: fft_stage<16, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 15: fft_stage<15, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 9: fft_stage<9, T, MAXE>(buf, N, cnt, Ns, tw); break;
+      case 8: fft_stage<8, T, MAXE>(buf, N, cnt, Ns, tw); break;
       case 4: fft_stage<4, T, MAXE>(buf, N, cnt, Ns, tw); break;
       case 2: fft_stage<2, T, MAXE>(buf, N, cnt, Ns, tw); break;
       case 3: fft_stage<3, T, MAXE>(buf, N, cnt, Ns, tw); break;

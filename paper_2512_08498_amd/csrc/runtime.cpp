@@ -216,18 +216,27 @@ int64_t total_px(const gsr_ctx *c) {
 
 float *cam_part(const gsr_ctx *c, void *base) { return reinterpret_cast<float *>(static_cast<char *>(base) + c->lay.cam_part); }
 
-// Radices of an FFT of length n (4s first, then 2, 3, 5, 7); false if n has
-// another prime factor or needs more than 16 stages.
+// Stage radices of an FFT of length n: the fewest stages over the radices
+// the kernels implement (composites 27, 25, 20, 16, 15, 9, 8 and primes 7,
+// 5, 3, 2; ties to the larger first radix); false if n has a prime factor
+// above 7 or needs more than 16 stages.
 bool fft_radices(int n, uint8_t *fac, int32_t &nfac) {
-  nfac = 0;
-  for (int p : {4, 2, 3, 5, 7}) {
-    while (n % p == 0) {
-      if (nfac == 16) return false;
-      fac[nfac++] = (uint8_t)p;
-      n /= p;
-    }
+  static const int kRadices[] = {27, 25, 20, 16, 15, 9, 8, 7, 5, 4, 3, 2};
+  if (n < 1) return false;
+  std::vector<int> best(n + 1, 1 << 20), first(n + 1, 0);
+  best[1] = 0;
+  for (int m = 2; m <= n; ++m) {
+    if (n % m != 0) continue;
+    for (int p : kRadices)
+      if (m % p == 0 && best[m / p] + 1 < best[m]) {
+        best[m] = best[m / p] + 1;
+        first[m] = p;
+      }
   }
-  return n == 1;
+  if (best[n] > 16) return false;
+  nfac = 0;
+  for (int m = n; m > 1; m /= first[m]) fac[nfac++] = (uint8_t)first[m];
+  return true;
 }
 
 constexpr int kFreqMaxN = 2560;      // longest row or column transform (three LDS buffers of it)
