@@ -16,9 +16,10 @@
 // twice (their mirror W - j has the same magnitudes).  A last pass sums each
 // image's columns in order.
 //
-// The FFT is Stockham's self-sorting mixed-radix form (radices 4, 2, 3, 5,
-// 7), one stage per radix over all sequences of the workgroup at once (the
-// two packed rows, or the three channels' columns), in one LDS buffer:
+// The FFT is Stockham's self-sorting mixed-radix form (radices 2, 3, 4, 5,
+// 7 and the composites 8, 9, 15, 16, 20, 25, 27, planned for the fewest
+// stages), one stage per radix over all sequences of the workgroup at once
+// (the two packed rows, or the three channels' columns), in one LDS buffer:
 // every thread loads and transforms its butterflies in registers, then
 // stores them after a barrier.  The twiddles exp(-2 pi i t / N) come from a
 // table per transform length computed in double precision at plan time.
