@@ -54,6 +54,7 @@ __global__ __launch_bounds__(256) void k_log_prob(const ViewInfo *__restrict__ v
   const int t = blockIdx.x - base;
   const int x0 = (t % txs) * kTW, y0 = (t / txs) * kTH;
   constexpr int rows = kTH + 2 * R;
+  constexpr int RA = (R + 3) / 4 * 4;  // the filter radius rounded up to whole float4s
   float *A = lds;                    // [3][rows][kTW]: rows * g
   float *B = A + 3 * rows * kTW;     // [3][rows][kTW]: rows * h
   const int x = threadIdx.x & 63, yb = (threadIdx.x >> 6) * 4;
@@ -63,15 +64,33 @@ __global__ __launch_bounds__(256) void k_log_prob(const ViewInfo *__restrict__ v
     // horizontal pass straight from global memory: item = (row, group of
     // four columns); its 4 + 2R inputs per channel (border replicated) are
     // loaded into registers and give four a and four b values per channel
+    // rows 16-byte aligned: interior windows are read as aligned float4s
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)W * 4u) & 15u) == 0;
     for (int e = threadIdx.x; e < rows * (kTW / 4); e += 256) {
       const int r = e >> 4, c0 = (e & 15) * 4;
       const int gy = min(max(y0 + r - R, 0), H - 1);
+      const bool interior = vec && x0 + c0 - RA >= 0 && x0 + c0 + 4 + RA <= W;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         const float *row = src + ((int64_t)ch * H + gy) * W;
         float in[4 + 2 * R];
+        if (interior) {
+          const float4 *rv = reinterpret_cast<const float4 *>(row + x0 + c0 - RA);
+          float buf[4 + 2 * RA];
 #pragma unroll
-        for (int q = 0; q < 4 + 2 * R; ++q) in[q] = row[min(max(x0 + c0 + q - R, 0), W - 1)];
+          for (int k = 0; k < (4 + 2 * RA) / 4; ++k) {
+            const float4 t = rv[k];
+            buf[4 * k] = t.x;
+            buf[4 * k + 1] = t.y;
+            buf[4 * k + 2] = t.z;
+            buf[4 * k + 3] = t.w;
+          }
+#pragma unroll
+          for (int q = 0; q < 4 + 2 * R; ++q) in[q] = buf[q + RA - R];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4 + 2 * R; ++q) in[q] = row[min(max(x0 + c0 + q - R, 0), W - 1)];
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float a = 0.0f, b = 0.0f;
