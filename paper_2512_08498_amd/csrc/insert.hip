@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_log_prob(const ViewInfo *__restrict__ v
     const float *src = (img == 0 ? gt : rd) + 3 * vi.pix_off;
     // horizontal pass straight from global memory: item = (row, group of
     // four columns); its 4 + 2R inputs per channel (border replicated) are
-    // loaded into registers and give four a and four b values per channel
-    // rows 16-byte aligned: interior windows are read as aligned float4s
+    // loaded into registers and give four a and four b values per channel.
+    // With 16-byte aligned rows an interior item reads whole float4s.
     const bool vec = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)W * 4u) & 15u) == 0;
     for (int e = threadIdx.x; e < rows * (kTW / 4); e += 256) {
       const int r = e >> 4, c0 = (e & 15) * 4;
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) void k_ins_write(const ViewInfo *__restrict__ 
       while (v + 1 < n_views && views[v + 1].pix_off <= p) ++v;
       const ViewInfo vi = views[v];
       const Cam c = cams[v];
-      const int64_t local = p - vi.pix_off;
-      const int u = (int)(local % vi.w), row = (int)(local / vi.w);
+      const uint32_t local = (uint32_t)(p - vi.pix_off);  // a view's pixels fit 32 bits
+      const int row = (int)(local / (uint32_t)vi.w), u = (int)(local - (uint32_t)row * (uint32_t)vi.w);
       const float z = depth[p];
       const float xc = z * (((float)u + 0.5f - c.cx) / c.fx);
       const float yc = z * (((float)row + 0.5f - c.cy) / c.fy);
