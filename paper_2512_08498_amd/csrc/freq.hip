@@ -219,7 +219,7 @@ __device__ __forceinline__ void dft(float2 *v) {
 }
 
 constexpr int kRowThreads = 256;                // row pass: two sequences of length W
-constexpr int kColThreads = 512;                // column pass: three sequences of length H
+constexpr int kColThreads = 256;                // column pass: three sequences of length H
 constexpr int kRowMaxElems = 2 * 2560;
 constexpr int kColMaxElems = 3 * 2560;
 
