@@ -207,14 +207,28 @@ __global__ __launch_bounds__(256) void k_ins_write(const ViewInfo *__restrict__ 
   uint32_t block_total;
   const uint32_t before = block_excl_scan<256>(mine, scan_tmp, block_total);
   uint32_t k = offsets[blockIdx.x] + before;
+  if (bits == 0) return;
+  // view of the thread's first pixel (binary search), then forward at the
+  // (rare) view boundary inside its 16 pixels
+  int v = 0;
+  for (int hi = n_views - 1; v < hi;) {
+    const int mid = (v + hi + 1) >> 1;
+    if ((int64_t)views[mid].pix_off <= p0) v = mid;
+    else hi = mid - 1;
+  }
+  int64_t next = v + 1 < n_views ? (int64_t)views[v + 1].pix_off : INT64_MAX;
+  ViewInfo vi = views[v];
+  Cam c = cams[v];
   for (int i = 0; i < kPer; ++i) {
     if (!(bits >> i & 1u)) continue;
     const int64_t p = p0 + i;
+    while (p >= next) {
+      ++v;
+      vi = views[v];
+      c = cams[v];
+      next = v + 1 < n_views ? (int64_t)views[v + 1].pix_off : INT64_MAX;
+    }
     if ((int64_t)k < capacity) {
-      int v = 0;
-      while (v + 1 < n_views && views[v + 1].pix_off <= p) ++v;
-      const ViewInfo vi = views[v];
-      const Cam c = cams[v];
       const uint32_t local = (uint32_t)(p - vi.pix_off);  // a view's pixels fit 32 bits
       const int row = (int)(local / (uint32_t)vi.w), u = (int)(local - (uint32_t)row * (uint32_t)vi.w);
       const float z = depth[p];
