@@ -490,10 +490,12 @@ def main():
         ev[1].record()
         torch.cuda.synchronize(dev)
         m_ms = ev[0].elapsed_time(ev[1]) / reps
-        w0, h0 = rast.sizes[0]
+        k0 = int((res["pix"][:n_ins] < rast.pix_off[1]).sum().item())
         # per Gaussian: mean, log-scale, DC colour read twice, match written and
-        # read, keep and colour written; per pixel of the view: the slot map
-        mbytes = scene.n * (2 * 36 + 8 + 1 + 12) + w0 * h0 * 4
+        # read, keep and colour written; per sample of the view: its pixel read
+        # twice, slot and group written, its colour and P(I) read, keep and
+        # colour written
+        mbytes = scene.n * (2 * 36 + 8 + 1 + 12) + k0 * (8 + 4 + 36 + 12 + 4 + 13)
         ins["merge"] = {"ms": m_ms, "bytes": mbytes, "hbm_frac": mbytes / (m_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                         "removed": int((mres["keep"][:scene.n] == 0).sum().item())}
         log(f"merge of {scene.n} Gaussians with view 0's samples: {m_ms:.3f} ms "

@@ -413,7 +413,8 @@ gsr_status gsr_log_insert(gsr_ctx *ctx, const gsr_camera *cams, const float *gt,
  * Gaussians' DC colour Y0 sh_0 + 1/2, the sample's ground-truth pixel gt).
  * Outputs: keep [n] and colour [3][n] (RGB, planar) for the Gaussians,
  * keep_new and colour_new [capacity][3] for the view's samples (entries of
- * other views untouched).  Deterministic (integer atomics only).
+ * other views untouched).  Deterministic (integer atomics only).  A pixel
+ * must appear at most once in the sample list, as gsr_log_insert writes it.
  * workspace: DEVICE, 256-byte aligned, gsr_merge_workspace(n) bytes (40
  * bytes per pixel of the largest view plus 4 per Gaussian).  The paper
  * leaves tau_d open, and the re-alignment of depths unspecified (not done). */

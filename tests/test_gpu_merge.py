@@ -55,14 +55,14 @@ def _compare(res, ref, n, k):
     return int((ref["match"] >= 0).sum())
 
 
-@pytest.mark.parametrize("kappa", [1.0, 2.0])
-def test_merge_small_view(kappa):
-    rng = np.random.default_rng(60)
+def _small_view_case(seed):
+    """A 48x32 posed view (view 1 of two) with K samples at random pixels and
+    N Gaussians, half of them placed near the samples' back-projections."""
+    rng = np.random.default_rng(seed)
     a = 0.15
     R = np.array([[math.cos(a), 0, math.sin(a)], [0, 1, 0], [-math.sin(a), 0, math.cos(a)]])
     cams = [camera(f=50.0, w=40, h=30), camera(f=60.0, w=48, h=32, R=R, t=np.array([0.1, 0.0, -0.2]))]
     rast = Rasterizer(cams, 1, 0)
-    view = 1
     W, H = 48, 32
     K, N = 80, 600
     pix = np.sort(rng.choice(W * H, K, replace=False))
@@ -81,17 +81,46 @@ def test_merge_small_view(kappa):
     sh = rng.normal(0, 1, (1, 3, N)).astype(np.float32)
     gt = rng.uniform(0, 1, 3 * rast.total_px).astype(np.float32)
     p = rng.uniform(0.05, 1.0, rast.total_px).astype(np.float32)
-    host, dev = _samples_for(rast, cams, view, pix, centres, gt)
-    dev["p_gt"] = torch.from_numpy(p).cuda()
     ex = {k_: torch.from_numpy(np.ascontiguousarray(v_)).cuda() for k_, v_ in
           (("mean", mean), ("log_scale", ls), ("sh", sh))}
-    res = rast.merge(ex, view, torch.from_numpy(gt).cuda(), dev, tau_d=0.4, kappa=kappa)
-    torch.cuda.synchronize()
     p_view = p[rast.pix_off[1]:rast.pix_off[2]].reshape(H, W)
+    return rast, cams, pix, centres, (mean, ls, sh), ex, gt, p, p_view
+
+
+def _merge_small(rast, cams, pix, centres, params, ex, gt, p, p_view, kappa):
+    host, dev = _samples_for(rast, cams, 1, pix, centres, gt)
+    dev["p_gt"] = torch.from_numpy(p).cuda()
+    res = rast.merge(ex, 1, torch.from_numpy(gt).cuda(), dev, tau_d=0.4, kappa=kappa)
+    torch.cuda.synchronize()
+    mean, ls, sh = params
     ref = merge(mean, ls, sh[0], cams[1], host, p_view, tau_d=0.4, kappa=kappa)
+    return res, ref
+
+
+@pytest.mark.parametrize("kappa", [1.0, 2.0])
+def test_merge_small_view(kappa):
+    rast, cams, pix, centres, params, ex, gt, p, p_view = _small_view_case(60)
+    res, ref = _merge_small(rast, cams, pix, centres, params, ex, gt, p, p_view, kappa)
+    K, N = len(pix), params[0].shape[1]
     assert _compare(res, ref, N, K) > 50
     # the spare entries (and any other view's) are untouched
     assert not res["keep_new"][K:].any()
+
+
+def test_merge_twice_on_one_workspace():
+    """The pixel -> sample map in the workspace is not cleared between calls:
+    a second merge with a third of the samples, at other list positions, must
+    ignore what the first left behind (pixels it sampled that the second does not, indices
+    that now name other pixels or lie past the count)."""
+    rast, cams, pix, centres, params, ex, gt, p, p_view = _small_view_case(63)
+    N = params[0].shape[1]
+    res, ref = _merge_small(rast, cams, pix, centres, params, ex, gt, p, p_view, 1.0)
+    assert _compare(res, ref, N, len(pix)) > 50
+    sel = np.sort(np.random.default_rng(64).permutation(len(pix))[:len(pix) // 3])
+    ws = rast._merge_ws.data_ptr()
+    res2, ref2 = _merge_small(rast, cams, pix[sel], centres[sel], params, ex, gt, p, p_view, 1.0)
+    assert rast._merge_ws.data_ptr() == ws
+    assert 10 < _compare(res2, ref2, N, len(sel)) < int((ref["match"] >= 0).sum())
 
 
 def test_merge_rig_views_with_the_scene():
