@@ -486,7 +486,7 @@ def main():
         mres = rast.merge(params, 0, g_d, res, tau_d=50.0)
         ev[0].record()
         for _ in range(reps):
-            mres = rast.merge(params, 0, g_d, res, tau_d=50.0)
+            mres = rast.merge(params, 0, g_d, res, tau_d=50.0, out=mres)
         ev[1].record()
         torch.cuda.synchronize(dev)
         m_ms = ev[0].elapsed_time(ev[1]) / reps

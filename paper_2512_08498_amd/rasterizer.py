@@ -364,7 +364,7 @@ class Rasterizer:
         res = dict(p_gt=torch.empty(px, **f32), p_render=torch.empty(px, **f32) if p_render else None,
                    pix=torch.empty(max(cap, 1), dtype=torch.int32, device=self.device),
                    scale=torch.empty(max(cap, 1), **f32), mean=torch.empty(max(cap, 1), 3, **f32),
-                   count=torch.zeros(1, dtype=torch.int32, device=self.device))
+                   count=torch.empty(1, dtype=torch.int32, device=self.device))
         out = L.InsertOut(res["pix"].data_ptr(), res["scale"].data_ptr(), res["mean"].data_ptr(),
                           res["count"].data_ptr(), cap)
         cams = cams_dev if cams_dev is not None else self.cams_dev
@@ -374,11 +374,14 @@ class Rasterizer:
                                             _vp(self._ins_ws), self._ins_ws.numel(), self.stream()))
         return res
 
-    def merge(self, existing, view, gt, ins, tau_d, kappa=1.0, cams_dev=None):
+    def merge(self, existing, view, gt, ins, tau_d, kappa=1.0, cams_dev=None, out=None):
         """Merge the existing Gaussians (dict with mean [3, n], log_scale
         [3, n], sh [K, 3, n]) with the samples of ``view`` from ``ins`` (a
         log_insert result): returns dict(keep [n] uint8, colour [3, n],
-        keep_new [capacity] uint8, colour_new [capacity, 3]) (see gsr_merge)."""
+        keep_new [capacity] uint8, colour_new [capacity, 3]) (see gsr_merge).
+        New result tensors have keep_new and colour_new zeroed; ``out`` (a
+        dict of that form, e.g. an earlier result) is written in place
+        instead, where the entries of other views' samples keep their values."""
         n = existing["mean"].shape[1]
         k = existing["sh"].shape[0]
         deg = int(round(k ** 0.5)) - 1
@@ -398,10 +401,19 @@ class Rasterizer:
         ws = getattr(self, "_merge_ws", None)
         if ws is None or ws.numel() < int(nb.value):
             ws = self._merge_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        res = dict(keep=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
-                   colour=torch.empty(3, max(n, 1), dtype=torch.float32, device=self.device),
-                   keep_new=torch.zeros(cap, dtype=torch.uint8, device=self.device),
-                   colour_new=torch.zeros(cap, 3, dtype=torch.float32, device=self.device))
+        if out is None:
+            res = dict(keep=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
+                       colour=torch.empty(3, max(n, 1), dtype=torch.float32, device=self.device),
+                       keep_new=torch.zeros(cap, dtype=torch.uint8, device=self.device),
+                       colour_new=torch.zeros(cap, 3, dtype=torch.float32, device=self.device))
+        else:
+            res = out
+            for name, dtype, shape in (("keep", torch.uint8, (max(n, 1),)), ("colour", torch.float32, (3, max(n, 1))),
+                                       ("keep_new", torch.uint8, (cap,)), ("colour_new", torch.float32, (cap, 3))):
+                t = res[name]
+                if t.dtype != dtype or not t.is_contiguous() or t.device != self.device or tuple(t.shape) != shape:
+                    raise ValueError(f"out[{name}]: expected contiguous {dtype} {shape} on {self.device}, got "
+                                     f"{t.dtype} {tuple(t.shape)} on {t.device}")
         g = L.Gaussians(n, deg, existing["mean"].data_ptr(), existing["log_scale"].data_ptr(), None, None,
                         existing["sh"].data_ptr())
         so = L.InsertOut(ins["pix"].data_ptr(), ins["scale"].data_ptr(), ins["mean"].data_ptr(),

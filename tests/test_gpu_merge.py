@@ -105,6 +105,16 @@ def test_merge_small_view(kappa):
     assert _compare(res, ref, N, K) > 50
     # the spare entries (and any other view's) are untouched
     assert not res["keep_new"][K:].any()
+    # written in place into an earlier result: the same outputs, spare entries kept
+    for v_ in res.values():
+        v_.fill_(7)
+    _, dev = _samples_for(rast, cams, 1, pix, centres, gt)
+    dev["p_gt"] = torch.from_numpy(p).cuda()
+    res2 = rast.merge(ex, 1, torch.from_numpy(gt).cuda(), dev, tau_d=0.4, kappa=kappa, out=res)
+    torch.cuda.synchronize()
+    assert res2 is res
+    _compare(res, ref, N, K)
+    assert (res["keep_new"][K:] == 7).all() and (res["colour_new"][K:] == 7).all()
 
 
 def test_merge_twice_on_one_workspace():
