@@ -160,24 +160,34 @@ __global__ __launch_bounds__(256) void k_ins_count(const uint8_t *__restrict__ m
 // Exclusive offsets of the blocks' counts and the total (one workgroup).
 __global__ __launch_bounds__(1024) void k_ins_scan(const uint32_t *__restrict__ counts, uint32_t nb,
                                                    uint32_t *__restrict__ offsets, uint32_t *__restrict__ total) {
-  __shared__ uint32_t part[1024];
+  __shared__ uint32_t wsum[16];
   const uint32_t per = (nb + 1023) / 1024;
   const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t s = 0;
   for (uint32_t b = b0; b < b1; ++b) s += counts[b];
-  part[threadIdx.x] = s;
+  // inclusive scan of the threads' sums: within each wave by shuffles, then
+  // over the 16 wave totals in the first wave
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const uint32_t x = part[i];
-      part[i] = acc;
-      acc += x;
+  if (w == 0) {
+    uint32_t t = lane < 16 ? wsum[lane] : 0u;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const uint32_t y = __shfl_up(t, d);
+      if (lane >= (uint32_t)d) t += y;
     }
-    *total = acc;
+    if (lane < 16) wsum[lane] = t;
   }
   __syncthreads();
-  uint32_t acc = part[threadIdx.x];
+  if (threadIdx.x == 1023) *total = wsum[15];
+  uint32_t acc = x - s + (w > 0 ? wsum[w - 1] : 0u);
   for (uint32_t b = b0; b < b1; ++b) {
     offsets[b] = acc;
     acc += counts[b];
