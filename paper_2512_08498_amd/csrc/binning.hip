@@ -158,8 +158,9 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_hist(const uint32_t *__restric
   hist[t * gridDim.x + blockIdx.x] = h[t];
 }
 
-// Device-wide exclusive scan of data[0, len): chunk sums, a single-block
-// scan of the sums, then each chunk scanned with its offset.  Global
+// Device-wide exclusive scan of data[0, len): chunk sums, then each chunk
+// scanned with its offset, the sum of the totals before it (added up by the
+// chunk's own workgroup, or over many chunks by a single-block scan).  Global
 // accesses are coalesced; the per-thread runs of 16 words are read from LDS
 // with a skew of one word per 16, so the 64 lanes hit distinct banks.
 __device__ __forceinline__ uint32_t skew(uint32_t j) { return j + (j >> 4); }
@@ -237,11 +238,24 @@ __global__ __launch_bounds__(1024) void k_scan_one(uint32_t *__restrict__ data, 
   for (uint32_t base = 0; base < len; base += 1024u * 16u) carry += scan_chunk<1024>(data, base, len, carry, lds, red);
 }
 
+// SUM_BEFORE: part holds the chunk totals, and each workgroup adds up those
+// before its chunk itself (at most kScanFusedMax words, read from L2), which
+// saves the launch of the single-block scan of the totals.  Otherwise part
+// holds the chunks' offsets.
+template <bool SUM_BEFORE>
 __global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *__restrict__ data, uint32_t len,
                                                        const uint32_t *__restrict__ part) {
   __shared__ uint32_t lds[kScanChunk + kScanChunk / 16];
   __shared__ uint32_t red[kScanNT / kWave];
-  scan_chunk<kScanNT>(data, blockIdx.x * kScanChunk, len, part[blockIdx.x], lds, red);
+  uint32_t carry;
+  if (SUM_BEFORE) {
+    uint32_t c = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanNT) c += part[i];
+    block_excl_scan<kScanNT>(c, red, carry);
+  } else {
+    carry = part[blockIdx.x];
+  }
+  scan_chunk<kScanNT>(data, blockIdx.x * kScanChunk, len, carry, lds, red);
 }
 
 // 2b. Stable scatter of one block's chunk by digit.  Wave w owns the w-th
@@ -407,6 +421,7 @@ __global__ __launch_bounds__(256) void k_tile_classify(Ws ws, Sizes sz, uint32_t
 namespace {
 
 constexpr uint32_t kScanOneMax = 1u << 16;  // scans up to this length take one workgroup
+constexpr uint32_t kScanFusedMax = 1024;    // chunks up to which each adds up the totals before it
 
 // Exclusive scan of len words in place, part holding ceil(len / 4096) words.
 void scan_words(uint32_t *data, uint32_t len, uint32_t *part, hipStream_t st) {
@@ -417,8 +432,12 @@ void scan_words(uint32_t *data, uint32_t len, uint32_t *part, hipStream_t st) {
   }
   const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
   k_scan_reduce<<<nb, kScanNT, 0, st>>>(data, len, part);
+  if (nb <= kScanFusedMax) {
+    k_scan_down<true><<<nb, kScanNT, 0, st>>>(data, len, part);
+    return;
+  }
   k_scan_top<<<1, 1024, 0, st>>>(part, nb);
-  k_scan_down<<<nb, kScanNT, 0, st>>>(data, len, part);
+  k_scan_down<false><<<nb, kScanNT, 0, st>>>(data, len, part);
 }
 
 uint32_t rdx_chunk(uint32_t cap) { return cap >= kRdxBig ? kRdxNT * 32u : kRdxNT * 8u; }
