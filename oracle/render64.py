@@ -71,7 +71,8 @@ def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p
     """Render one view (or the pixel window (x0, x1, y0, y1), half-open).
 
     Returns dict: image [3,h,w], T [h,w], count [h,w], last [h,w] (Gaussian
-    index, -1 if none), ambiguous [h,w], wsum [h,w] (sum of alpha*T), and with
+    index, -1 if none), ambiguous [h,w], wsum [h,w] (sum of alpha*T), capped
+    [h,w] (composited entries whose o G exceeded the 0.99 cap), and with
     ``record`` the composited entries (pixel flat index, Gaussian) in order.
     """
     W, H = int(cam.width), int(cam.height)
@@ -88,6 +89,7 @@ def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p
     T = np.ones((h, w))
     wsum = np.zeros((h, w))
     count = np.zeros((h, w), dtype=np.int64)
+    capped = np.zeros((h, w), dtype=np.int64)
     last = np.full((h, w), -1, dtype=np.int64)
     done = np.zeros((h, w), dtype=bool)
     amb = np.zeros((h, w), dtype=bool)
@@ -123,6 +125,7 @@ def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p
         wsum[sl] += wgt
         T[sl] = np.where(comp, Tn, Tp)
         count[sl] += comp
+        capped[sl] += comp & (raw > ALPHA_MAX)
         last[sl] = np.where(comp, g, last[sl])
         done[sl] |= stop
         if record and comp.any():
@@ -130,7 +133,7 @@ def render_view(scene_arrays, sh_degree, cam, bg=(0.0, 0.0, 0.0), window=None, p
             rec_g.append(np.full(int(comp.sum()), g, dtype=np.int64))
 
     out = dict(image=C + T[None] * bg[:, None, None], T=T, count=count, last=last,
-               ambiguous=amb, wsum=wsum, window=(x0, x1, y0, y1))
+               ambiguous=amb, wsum=wsum, capped=capped, window=(x0, x1, y0, y1))
     if record:
         if rec_pix:
             pix = np.concatenate(rec_pix)

@@ -276,15 +276,14 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
   }
 }
 
-// 16 px tiles.  Tiles whose list has at least kLongList entries (a prefix
-// of the longest-first order) take a whole workgroup: four waves, each an
+// 16 px tiles.  Tiles whose list has at least Sizes::long_list entries (a
+// prefix of the longest-first order, autotuned) take a whole workgroup: four waves, each an
 // 8 x 8 quadrant with one pixel per lane, sharing 128-record LDS batches,
 // so a long list is walked four times faster.  The remaining tiles are
 // packed four to a workgroup, one wave each (16 x 16 pixels, four per lane),
 // so each record's wave reduction is paid once per tile; neighbours in the
 // longest-first order have similar lengths, so the four waves finish
 // together.
-constexpr uint32_t kLongList = 512;
 
 union BwdLds16 {
   BwdLds<128, 4> quad;
@@ -356,10 +355,12 @@ __device__ __forceinline__ void add_partial(const float4 *__restrict__ src, floa
 }
 
 // step (optional): the Adam step counter, incremented here (before the
-// per-Gaussian kernel that reads it) rather than by a launch of its own.
+// per-Gaussian kernel that reads it) rather than by a launch of its own.  On
+// a capacity overflow nothing is updated (the per-Gaussian kernel skips its
+// Adam step too), so the counter stays with the moments.
 __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
-  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
   if (ws.scalars[kOverflow]) return;
+  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
   const uint32_t nrec = ws.scalars[kNumRecords];
   const int lane = lane_id();
   const uint32_t wave_stride = gridDim.x * (blockDim.x / kWave) * kWave;

@@ -83,6 +83,9 @@ class Rasterizer:
         L.check(None, self.lib.gsr_create(C.byref(self.ctx)))
         self.workspace = None
         self.rig = None
+        # bumped by every call that rewrites the workspace's binning state (a
+        # plan or a forward), so a backward can tell that its state is gone
+        self.generation = 0
         self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(self.tile_size or 16, long_list, 0.0))))
         self._plan(capacity_records, capacity_pairs)
 
@@ -101,6 +104,7 @@ class Rasterizer:
         self._ins_ws = None
         self._merge_ws = None
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.generation += 1
 
     def tuning(self):
         t = L.Tuning()
@@ -183,6 +187,7 @@ class Rasterizer:
         out = out if out is not None else self.new_fwd_out()
         g = self._gaussians(params)
         cams = cams_dev if cams_dev is not None else self.cams_dev
+        self.generation += 1
         self._check(self.lib.gsr_render_forward(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
                                                 self.ws_bytes, C.byref(self._fwd_struct(out)), self.stream()))
         if check:
@@ -204,6 +209,7 @@ class Rasterizer:
         dl_out = dl_out if dl_out is not None else torch.empty_like(out["image"])
         g = self._gaussians(params)
         cams = cams_dev if cams_dev is not None else self.cams_dev
+        self.generation += 1
         self._check(self.lib.gsr_render_forward_l1(self.ctx, C.byref(g), _vp(cams), self.views, _vp(self.workspace),
                                                    self.ws_bytes, C.byref(self._fwd_struct(out)), _vp(target),
                                                    _vp(loss_out), _vp(dl_out), self.stream()))
@@ -481,8 +487,13 @@ class FusedAdam:
 class RasterizeFn(torch.autograd.Function):
     """image = render(Gaussians) with the hand-written adjoint as backward.
 
-    The workspace of ``rast`` carries the binning state from forward to
-    backward, so no other forward of the same rasterizer may run in between.
+    The workspace of ``rast`` carries the binning state (records, tile lists)
+    from the forward to the backward.  A later forward or re-plan of the same
+    rasterizer overwrites it; the backward then raises rather than return
+    gradients of another state (each forward is stamped with the
+    rasterizer's generation).  The forward's per-pixel outputs (final
+    transmittance, last position, contributor count) stay available as
+    ``rast.last_forward``.
     """
 
     @staticmethod
@@ -490,14 +501,19 @@ class RasterizeFn(torch.autograd.Function):
         params = dict(mean=mean.contiguous(), log_scale=log_scale.contiguous(), quat=quat.contiguous(),
                       opacity_logit=opacity_logit.contiguous(), sh=sh.contiguous())
         out = rast.forward(params)
+        rast.last_forward = out
         ctx.rast = rast
         ctx.fwd = out
+        ctx.generation = rast.generation
         ctx.save_for_backward(*(params[k] for k in PARAM_NAMES))
-        ctx.mark_non_differentiable(out["t_final"])
         return out["image"]
 
     @staticmethod
     def backward(ctx, d_image):
+        if ctx.rast.generation != ctx.generation:
+            raise RuntimeError("RasterizeFn.backward: the rasterizer ran another forward or re-planned after this "
+                               "forward, so its workspace no longer holds this forward's binning state; call "
+                               "backward before the next forward of the same Rasterizer (or use one per graph)")
         params = dict(zip(PARAM_NAMES, ctx.saved_tensors))
         grads = ctx.rast.backward(params, ctx.fwd, d_image.contiguous())
         return (None,) + tuple(grads[k] for k in PARAM_NAMES)

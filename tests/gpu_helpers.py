@@ -56,3 +56,20 @@ def grads_to_host(grads):
     if "camera" in grads:
         out["cam"] = grads["camera"].cpu().numpy().astype(np.float64)
     return out
+
+
+def compare_grads(gpu, ora, tol=1e-4):
+    """Gradient bar: per group, max |gpu - oracle| <= tol * max |oracle|, and
+    tol relative elementwise on entries of at least 1e-2 of that maximum; a
+    group that is zero in the oracle must be exactly zero."""
+    for k in ora:
+        scale = np.abs(ora[k]).max()
+        if scale == 0:
+            assert np.abs(gpu[k]).max() == 0, k
+            continue
+        diff = np.abs(gpu[k] - ora[k])
+        big = np.abs(ora[k]) >= 1e-2 * scale
+        rel = (diff[big] / np.abs(ora[k][big])).max() if big.any() else 0.0
+        log(f"  grad {k}: max |diff|/max|g| {diff.max() / scale:.2e}, max rel (big) {rel:.2e}")
+        assert diff.max() <= tol * scale, k
+        assert rel <= tol, k

@@ -6,9 +6,10 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import device_params, grads_to_host, host_outputs, log, render_gpu
+from gpu_helpers import compare_grads, device_params, grads_to_host, host_outputs, log, render_gpu
 from oracle.adam64 import adam_step
 from oracle.binning import tile_lists
+from oracle.grad64 import grad64
 from oracle.render64 import render
 from paper_2512_08498_amd import PARAM_NAMES, FusedAdam, Rasterizer
 from paper_2512_08498_amd import _lib as L
@@ -264,10 +265,15 @@ def _edge_check(sc, cams, ts=16):
         keys, vals, csr = rast.debug_binning()
         okeys, ovals, ocsr = tile_lists(sc, cams, ts)
         assert np.array_equal(keys, okeys) and np.array_equal(vals, ovals) and np.array_equal(csr, ocsr)
-        dl = torch.ones(3 * rast.total_px, device="cuda") * 1e-3
-        grads = rast.backward(params, out, dl)
-        for k in PARAM_NAMES:
-            assert torch.isfinite(grads[k]).all(), k
+        # gradients against the oracle's, under a random cotangent masked to
+        # the non-ambiguous pixels (all zero where nothing composites)
+        rng = np.random.default_rng(sc.n + 7 * ts)
+        cots = [np.where(o["ambiguous"][None], 0.0,
+                         (rng.standard_normal((3, c.height, c.width)) * 1e-3).astype(np.float32).astype(np.float64))
+                for o, c in zip(ora, cams)]
+        dl = torch.from_numpy(np.concatenate([c.astype(np.float32).reshape(-1) for c in cots])).cuda()
+        grads = grads_to_host(rast.backward(params, out, dl))
+        compare_grads(grads, grad64(sc, cams, cots))
     return rast
 
 
@@ -344,3 +350,26 @@ def test_streaming_copy():
         assert torch.equal(dst, src)
     with pytest.raises(GsrError):
         device_copy(torch.zeros(3, dtype=torch.int32, device="cuda"), torch.zeros(3, dtype=torch.int32, device="cuda"))
+
+
+def test_overflowed_step_leaves_adam_state_untouched(cfg1):
+    """A fused backward + Adam step after a forward that overflowed its
+    capacity (as a graph replay with no check would run it) updates nothing:
+    not the parameters, not the moments and not the step counter, so the
+    bias correction stays in step with the moments."""
+    scene_, cams, _ = cfg1
+    rast = Rasterizer(cams, scene_.n, scene_.sh_degree, capacity_records=10, capacity_pairs=10)
+    params = device_params(scene_)
+    before = {k: v.clone() for k, v in params.items()}
+    opt = FusedAdam(rast, params)
+    out = rast.new_fwd_out()
+    rast.forward(params, out=out, check=False)
+    dl = torch.full((3 * rast.total_px,), 1e-3, device="cuda")
+    rast.backward_adam(params, out, dl, opt)
+    torch.cuda.synchronize()
+    assert int(opt.step.item()) == 0
+    for k in PARAM_NAMES:
+        assert torch.equal(params[k], before[k]), k
+        assert not opt.m[k].any() and not opt.v[k].any(), k
+    with pytest.raises(L.GsrError):
+        rast.check()

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import device_params, grads_to_host, host_outputs, last_gaussian, log, render_gpu
+from gpu_helpers import compare_grads, device_params, grads_to_host, host_outputs, last_gaussian, log, \
+    render_gpu
 from oracle.binning import tile_lists
 from oracle.grad64 import grad64
 from oracle.render64 import render
@@ -72,27 +73,24 @@ def _masked_cotangent(oracle, targets):
 
 
 def _compare_grads(gpu, ora, tol=GRAD_TOL):
-    for k in ora:
-        scale = np.abs(ora[k]).max()
-        if scale == 0:
-            assert np.abs(gpu[k]).max() == 0, k
-            continue
-        diff = np.abs(gpu[k] - ora[k])
-        big = np.abs(ora[k]) >= 1e-2 * scale
-        rel = (diff[big] / np.abs(ora[k][big])).max() if big.any() else 0.0
-        log(f"  grad {k}: max |diff|/max|g| {diff.max() / scale:.2e}, max rel (big) {rel:.2e}")
-        assert diff.max() <= tol * scale, k
-        assert rel <= tol, k
+    compare_grads(gpu, ora, tol)
 
 
-def _check_backward(scene, cams, targets, ts=16, **kw):
-    oracle = render(scene, cams)
-    cots = _masked_cotangent(oracle, targets)
+def _check_backward(scene, cams, targets, ts=16, cots=None, cam_grads=False, oracle=None, **kw):
+    """GPU gradients (and with cam_grads the views' pose gradients) against
+    grad64 under the masked L1 cotangent of ``targets``, or under ``cots``
+    (per-view [3, H, W], zeroed here on ambiguous pixels)."""
+    oracle = oracle if oracle is not None else render(scene, cams)
+    if cots is None:
+        cots = _masked_cotangent(oracle, targets)
+    else:
+        cots = [np.where(o["ambiguous"][None], 0.0, c.astype(np.float32).astype(np.float64))
+                for o, c in zip(oracle, cots)]
     rast, params, out = render_gpu(scene, cams, ts=ts, **kw)
     dl = torch.from_numpy(np.concatenate([c.astype(np.float32).reshape(-1) for c in cots])).cuda()
-    grads = rast.backward(params, out, dl)
+    grads = rast.backward(params, out, dl, cam_grads=True if cam_grads else None)
     torch.cuda.synchronize()
-    _compare_grads(grads_to_host(grads), grad64(scene, cams, cots))
+    _compare_grads(grads_to_host(grads), grad64(scene, cams, cots, cam_grads=cam_grads))
 
 
 @pytest.mark.parametrize("ts", [16, 8, 32])
@@ -209,3 +207,49 @@ def test_evaluation_count_rig():
     lo, hi = _oracle_evaluations(scene, cams, oracle)
     log(f"mini rig: evaluations {got}, oracle [{lo}, {hi}]")
     assert lo <= got <= hi
+
+
+@pytest.mark.parametrize("ts,long_list", [(16, 1024), (16, 0), (16, 0xFFFFFFFF), (8, 1024), (32, 1024)])
+def test_alpha_cap_scene(ts, long_list):
+    """Opaque Gaussians whose o G exceeds 0.99 at >= 100 composited entries:
+    alpha takes the cap there and its derivative in opacity and falloff is
+    zero (the oracle's FP64 gradient, pinned by finite differences at these
+    entries).  Forward and gradients at the usual bars, with a cotangent that
+    weighs the capped pixels 30x, for both backward walks at 16 px."""
+    from tiny_scenes import capped
+
+    scene, cams = capped()
+    oracle = render(scene, cams)
+    n_cap = int(oracle[0]["capped"].sum())
+    log(f"alpha cap ts={ts} long_list={long_list}: {n_cap} capped entries, "
+        f"{int(oracle[0]['ambiguous'].sum())} ambiguous pixels")
+    assert n_cap >= 100
+    _check_forward(scene, cams, ts, oracle=oracle)
+    rng = np.random.default_rng(31)
+    cot = rng.standard_normal((3, cams[0].height, cams[0].width)) * 1e-3
+    cot *= (1.0 + 30.0 * (oracle[0]["capped"] > 0))[None]
+    _check_backward(scene, cams, None, ts, cots=[cot], oracle=oracle, long_list=long_list)
+
+
+@pytest.mark.parametrize("ts,long_list", [(16, 1024), (16, 0), (16, 0xFFFFFFFF), (8, 1024), (32, 1024)])
+def test_guard_clamp_scene(ts, long_list):
+    """Large Gaussians centred beyond the Jacobian guard on every side of a
+    posed view (SH degree 3) whose footprints reach the image: J is built
+    from the clamped x/z and y/z, whose derivative is zero (pinned by finite
+    differences).  Forward, Gaussian gradients and the view's pose gradient
+    against the oracle."""
+    from oracle.render64 import render_view
+    from tiny_scenes import guard_clamped, guard_clamped_ids
+
+    scene, cams = guard_clamped()
+    oracle = render(scene, cams)
+    ids = guard_clamped_ids(scene, cams)[0]
+    _, gg = render_view(scene.arrays(), scene.sh_degree, cams[0], record=True)["entries"]
+    reached = int(sum((gg == g).sum() >= 50 for g in ids))
+    log(f"guard clamp ts={ts} long_list={long_list}: {len(ids)} clamped Gaussians, {reached} composited "
+        f"at >= 50 pixels")
+    assert reached >= 8
+    _check_forward(scene, cams, ts, oracle=oracle)
+    rng = np.random.default_rng(41)
+    targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
+    _check_backward(scene, cams, targets, ts, cam_grads=True, oracle=oracle, long_list=long_list)

@@ -12,10 +12,10 @@ from oracle.render64 import render
 from tiny_scenes import mini_rig
 
 
-def _check_fd(scene, cams, cot, grads, picks, rel=1e-6):
+def _check_fd(scene, cams, cot, grads, picks, rel=1e-6, h_rel=1e-6):
     checked = 0
     for name, flat in picks:
-        fd, valid = fd_gradient(scene, cams, cot, name, flat)
+        fd, valid = fd_gradient(scene, cams, cot, name, flat, h_rel=h_rel)
         if not valid:
             continue
         ad = grads[name].reshape(-1)[flat]
@@ -109,3 +109,63 @@ def test_adam_matches_torch_adam_float64():
         opt.step()
         p, m, v = adam_step(p, g, m, v, step, 3e-3)
     assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-13)
+
+
+def test_autograd_matches_finite_differences_at_the_alpha_cap():
+    """alpha = min(0.99, o G) has zero derivative in o and G where the cap
+    is active (reading of Sec. 3.3's gradients through the renderer).  The
+    scene holds >= 100 capped composited entries; the cotangent weighs the
+    pixels with a capped entry 30x, and the picks include the opacity,
+    position, scale and rotation of every capped Gaussian, so a gradient
+    passed through the cap (or dropped from uncapped pixels) fails."""
+    from oracle.render64 import render_view
+    from tiny_scenes import capped
+
+    scene, cams = capped()
+    o = render_view(scene.arrays(), scene.sh_degree, cams[0])
+    n_cap = int(o["capped"].sum())
+    assert n_cap >= 100 and not o["ambiguous"].any()
+    rng = np.random.default_rng(31)
+    cot = [rng.standard_normal((3, cams[0].height, cams[0].width)) * (1.0 + 30.0 * (o["capped"] > 0))[None]]
+    grads = grad64(scene, cams, cot)
+    opac = 1.0 / (1.0 + np.exp(-scene.opacity_logit.astype(np.float64)))
+    ids = np.nonzero(opac > 0.99)[0]
+    assert len(ids) >= 12
+    n = scene.n
+    picks = [("opacity_logit", int(g)) for g in ids]
+    picks += [("mean", int(c * n + g)) for g in ids for c in (0, 1)]
+    picks += [("log_scale", int(g)) for g in ids[::2]] + [("quat", int(n + g)) for g in ids[1::2]]
+    picks += _picks(scene, grads, rng, 6)
+    # opacity logits near 6 make dL/dtheta small (o (1 - o) ~ 3e-3): a step of
+    # 1e-5 keeps the difference quotient's rounding below the 1e-6 bar
+    assert _check_fd(scene, cams, cot, grads, picks, h_rel=1e-5) >= 60
+
+
+def test_autograd_matches_finite_differences_beyond_the_jacobian_guard():
+    """Where x/z (or y/z) lies beyond the guard, J is built from the clamped
+    value, which has zero derivative in x_c.  Ten large Gaussians centred
+    outside the guard on all sides of a posed view (SH degree 3) reach into
+    the image; FD of their positions, scales, rotations and SH coefficients
+    pins the clamp's derivative (and its absence from the unclamped
+    coordinate)."""
+    from oracle.render64 import render_view
+    from tiny_scenes import guard_clamped, guard_clamped_ids
+
+    scene, cams = guard_clamped()
+    ids = guard_clamped_ids(scene, cams)[0]
+    o = render_view(scene.arrays(), scene.sh_degree, cams[0], record=True)
+    _, gg = o["entries"]
+    reached = [int(g) for g in ids if (gg == g).sum() >= 50]
+    assert len(reached) >= 8
+    rng = np.random.default_rng(41)
+    cot = [rng.standard_normal((3, cams[0].height, cams[0].width))]
+    grads = grad64(scene, cams, cot)
+    n = scene.n
+    picks = []
+    for g in reached:
+        picks += [("mean", c * n + g) for c in range(3)]
+        picks += [("log_scale", c * n + g) for c in range(3)]
+        picks += [("quat", c * n + g) for c in (0, 2)]
+        picks += [("opacity_logit", g), ("sh", (5 * 3 + 1) * n + g)]
+    picks += _picks(scene, grads, rng, 4)
+    assert _check_fd(scene, cams, cot, grads, picks) >= 80

@@ -123,3 +123,89 @@ def test_spec_is_deterministic():
         assert np.array_equal(a[k], b[k])
     for x, y in zip(a["box"], b["box"]):
         assert np.array_equal(x, y)
+
+
+def _box64(scene, cam):
+    """The spec's pixel box recomputed in FP64: the bounding box of the
+    support ellipse d^2 <= 11.0826 around the projected mean (pixel i centred
+    at i + 1/2), with the dilated covariance from the torch projection.
+    Returns (z, bounds before clamping, the value each bound rounds)."""
+    z64, u64, v64 = _truth64(scene, cam)
+    pr = project_view(to_params64(scene.arrays()), scene.sh_degree, cam)
+    cov = pr["cov2"].numpy()
+    with np.errstate(all="ignore"):
+        hx = np.sqrt(11.0826 * cov[:, 0])
+        hy = np.sqrt(11.0826 * cov[:, 2])
+    raw = (u64 - hx - 0.5, u64 + hx - 0.5, v64 - hy - 0.5, v64 + hy - 0.5)
+    b = (np.ceil(raw[0]), np.floor(raw[1]), np.ceil(raw[2]), np.floor(raw[3]))
+    return z64, b, raw
+
+
+def test_spec_box_all_bounds_and_tile_rect_match_fp64():
+    """All four box bounds, the visibility decision and the tile rectangle at
+    8, 16 and 32 px equal their FP64 values on every Gaussian whose FP64
+    bounds are not within 1e-3 px of a rounding boundary (and whose depth is
+    not within 1e-6 of the near plane), over posed rig views and a full-HD
+    view.  A box one pixel too large (or too small) on either side, or a tile
+    rectangle off by one, fails."""
+    checked = 0
+    for cfg, scale in ((3, 0.01), (2, 0.02)):
+        scene, cams = make_config(cfg, scale=scale)
+        for cam in cams[:3]:
+            W, H = cam.width, cam.height
+            z64, b, raw = _box64(scene, cam)
+            near = np.abs(z64 - 0.2) <= 1e-6
+            safe = ~near
+            for r in raw:
+                with np.errstate(invalid="ignore"):
+                    safe &= np.isfinite(r) & (np.abs(r - np.round(r)) > 1e-3)
+            vis64 = (z64 > 0.2) & (b[0] <= b[1]) & (b[2] <= b[3]) & (b[1] >= 0) & (b[0] <= W - 1) & \
+                    (b[3] >= 0) & (b[2] <= H - 1)
+            i0 = np.clip(b[0], 0, W - 1)
+            i1 = np.clip(b[1], 0, W - 1)
+            j0 = np.clip(b[2], 0, H - 1)
+            j1 = np.clip(b[3], 0, H - 1)
+            for ts in (8, 16, 32):
+                s = spec32(scene.mean, scene.log_scale, scene.quat, cam, ts)
+                assert np.array_equal(s["visible"][safe], vis64[safe])
+                sv = safe & vis64
+                assert sv.sum() > 100
+                for got, want in zip(s["box"], (i0, i1, j0, j1)):
+                    assert np.array_equal(got[sv], want[sv].astype(np.int32))
+                for got, want in zip(s["rect"], (i0, i1, j0, j1)):
+                    assert np.array_equal(got[sv], (want[sv] // ts).astype(np.int32))
+                checked += int(sv.sum())
+    assert checked > 10000
+
+
+def test_spec_box_is_not_larger_than_needed():
+    """The box is the tight bounding box of the support ellipse d^2 <= 11.0826
+    (FP64): at a pixel-centre column x the least d^2 over all y is x^2/S_xx,
+    so the box's outermost columns (rows) reach the ellipse and the next ones
+    out do not, wherever the edge is not the image border."""
+    scene, cams = make_config(1)
+    cam = cams[0]
+    s = spec32(scene.mean, scene.log_scale, scene.quat, cam, 16)
+    idx = np.nonzero(s["visible"])[0]
+    pr = project_view(to_params64(scene.arrays()), 0, cam, index=idx)
+    mu, cov = pr["mu2"].numpy(), pr["cov2"].numpy()
+    k_in, k_out = 11.0826 * (1 + 1e-5), 11.0826 * (1 - 1e-5)
+    checked = 0
+    for k, g in enumerate(idx[:500]):
+        i0, i1, j0, j1 = (int(b[g]) for b in s["box"])
+        sxx, syy = cov[k, 0], cov[k, 2]
+        x0, x1 = i0 + 0.5 - mu[k, 0], i1 + 0.5 - mu[k, 0]
+        y0, y1 = j0 + 0.5 - mu[k, 1], j1 + 0.5 - mu[k, 1]
+        if i0 > 0:
+            assert x0 * x0 / sxx <= k_in and (x0 - 1) ** 2 / sxx > k_out, (g, "i0")
+            checked += 1
+        if i1 < cam.width - 1:
+            assert x1 * x1 / sxx <= k_in and (x1 + 1) ** 2 / sxx > k_out, (g, "i1")
+            checked += 1
+        if j0 > 0:
+            assert y0 * y0 / syy <= k_in and (y0 - 1) ** 2 / syy > k_out, (g, "j0")
+            checked += 1
+        if j1 < cam.height - 1:
+            assert y1 * y1 / syy <= k_in and (y1 + 1) ** 2 / syy > k_out, (g, "j1")
+            checked += 1
+    assert checked > 1000
