@@ -491,11 +491,12 @@ def main():
         torch.cuda.synchronize(dev)
         m_ms = ev[0].elapsed_time(ev[1]) / reps
         k0 = int((res["pix"][:n_ins] < rast.pix_off[1]).sum().item())
-        # per Gaussian: mean, log-scale, DC colour read twice, match written and
-        # read, keep and colour written; per sample of the view: its pixel read
-        # twice, slot and group written, its colour and P(I) read, keep and
-        # colour written
-        mbytes = scene.n * (2 * 36 + 8 + 1 + 12) + k0 * (8 + 4 + 36 + 12 + 4 + 13)
+        # per Gaussian: mean and DC colour read twice, log-scale once, match
+        # written and read, keep, colour and re-aligned mean written; per
+        # sample of the view: its pixel read twice, slot and group (count,
+        # colour and distance sums, winner key) written, its colour and centre
+        # read, keep, colour and centre written
+        mbytes = scene.n * (2 * 24 + 12 + 8 + 1 + 12 + 12) + k0 * (8 + 4 + 4 + 24 + 8 + 8 + 12 + 12 + 1 + 12 + 12)
         ins["merge"] = {"ms": m_ms, "bytes": mbytes, "hbm_frac": mbytes / (m_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                         "removed": int((mres["keep"][:scene.n] == 0).sum().item())}
         log(f"merge of {scene.n} Gaussians with view 0's samples: {m_ms:.3f} ms "

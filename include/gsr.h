@@ -401,23 +401,36 @@ gsr_status gsr_log_insert(gsr_ctx *ctx, const gsr_camera *cams, const float *gt,
 
 /* Per-camera merging (Sec. 3.2, Eqs. 7-8): before the samples of camera i
  * (gsr_log_insert's list; only those in view `view` are used) are added,
- * each existing Gaussian g (mean, log_scale and the degree-0 SH of `g`)
- * corresponds to the sample whose pixel contains its projection into the
- * view, if z > 0.2 and | |x_c| - d | <= tau_d (d the sample centre's
- * distance).  In each group of a sample and its corresponding Gaussians only
- * the smallest image-space scale survives -- s' = kappa S fx / |x_c| for a
- * Gaussian (S = exp of the mean log-scale; the paper prints kappa = 2, which
- * disagrees with Eqs. 6 and 8 by that factor), s = 1 / (2 sqrt(P(I))) for the
- * sample (p_gt from gsr_log_insert) -- existing Gaussians winning ties, the
- * lower index first, and the survivor takes the group's mean colour (the
- * Gaussians' DC colour Y0 sh_0 + 1/2, the sample's ground-truth pixel gt).
- * Outputs: keep [n] and colour [3][n] (RGB, planar) for the Gaussians,
- * keep_new and colour_new [capacity][3] for the view's samples (entries of
- * other views untouched).  Deterministic (integer atomics only).  A pixel
- * must appear at most once in the sample list, as gsr_log_insert writes it.
- * workspace: DEVICE, 256-byte aligned, gsr_merge_workspace(n) bytes (40
- * bytes per pixel of the largest view plus 4 per Gaussian).  The paper
- * leaves tau_d open, and the re-alignment of depths unspecified (not done). */
+ * each existing Gaussian g (mean, log_scale and the degree-0 SH of `g`) is
+ * reprojected into the view: x' = (fx x/z + cx, fy y/z + cy) of x_c = R mu + t,
+ * d' = |x_c|.  If z > 0.2 and x' lies in [0, W) x [0, H), g corresponds to the
+ * sampled pixel, among the four pixel centres around x', with the largest
+ * positive bilinear weight (lowest pixel index on equal weights; the paper
+ * matches x' and the sampled pixels by bilinear interpolation of P), provided
+ * | d' - d | <= tau_d (d the sample centre's distance).  Each member of a
+ * group (a sample and its corresponding Gaussians) is measured against the
+ * view's scale where it sits: rho = s' / s_i(x'), s' = kappa S fx / d' (S =
+ * exp of the mean log-scale; the paper prints kappa = 2, which disagrees with
+ * Eqs. 6 and 8 by that factor), s_i(x') = 1 / (2 sqrt(P(x'))) with P(I)
+ * (p_gt from gsr_log_insert) interpolated bilinearly at x', borders
+ * replicated; a sample's own rho is 1.  Only the smallest rho survives
+ * (existing Gaussians win ties, the lower index first); the survivor takes
+ * the group's mean colour (the Gaussians' DC colour Y0 sh_0 + 1/2, the
+ * sample's ground-truth pixel gt) and, re-aligning the depth (a reading: the
+ * paper does not say how), is moved along the view's ray through it to the
+ * group's mean distance.  The geometry is evaluated in double precision.
+ * Outputs (DEVICE): keep [n] and colour [3][n] (RGB, planar) for the
+ * Gaussians, keep_new and colour_new [capacity][3] for the view's samples
+ * (entries of other views untouched); optionally (NULL to skip) mean [3][n],
+ * the Gaussians' centres after the re-alignment (unchanged where not
+ * moved), and mean_new [capacity][3], the samples' centres likewise.
+ * Deterministic (integer atomics only).  A pixel must appear at most once in
+ * the sample list, as gsr_log_insert writes it.
+ * workspace: DEVICE, 256-byte aligned, gsr_merge_workspace(n) bytes (48
+ * bytes per pixel of the largest view plus 4 per Gaussian).  tau_d is open
+ * in the paper: a parameter.  Errors: GSR_ERR_INVALID_ARG for a NULL required
+ * pointer, a view out of range, tau_d < 0, kappa <= 0, a short or unaligned
+ * workspace; GSR_ERR_NOT_PLANNED before gsr_plan. */
 typedef struct {
   float tau_d;
   float kappa;
@@ -428,6 +441,8 @@ typedef struct {
   float *colour;
   uint8_t *keep_new;
   float *colour_new;
+  float *mean;     /* optional [3][n] */
+  float *mean_new; /* optional [capacity][3] */
 } gsr_merge_out;
 
 gsr_status gsr_merge_workspace(gsr_ctx *ctx, int64_t n, size_t *bytes);

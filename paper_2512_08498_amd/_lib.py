@@ -65,7 +65,7 @@ class MergeConfig(C.Structure):
 
 
 class MergeOut(C.Structure):
-    _fields_ = [("keep", P), ("colour", P), ("keep_new", P), ("colour_new", P)]
+    _fields_ = [("keep", P), ("colour", P), ("keep_new", P), ("colour_new", P), ("mean", P), ("mean_new", P)]
 
 
 class Moments(C.Structure):

@@ -85,11 +85,17 @@ void launch_log_insert(const ViewInfo *views_d, int n_views, uint32_t n_tiles, i
                        float *p_gt, float *p_rd, uint8_t *mask, uint32_t *counts, uint32_t *offsets,
                        uint32_t *total, uint32_t *out_pix, float *out_scale, float *out_mean, int64_t capacity,
                        hipStream_t st);
+// Per-pixel (of the view) and per-Gaussian scratch of the merge.
+struct MergeBufs {
+  int32_t *slot;
+  uint32_t *cnt;
+  unsigned long long *csum, *dsum, *win;
+  int32_t *match;
+};
 void launch_merge(const GaussPtrs &gp, int64_t n, const Cam *cams, int view, const ViewInfo &vi, const float *gt,
                   const float *p_gt, const uint32_t *pix, const float *s_mean, const uint32_t *count,
-                  int64_t capacity, float tau_d, float kappa, int32_t *slot, uint32_t *cnt, unsigned long long *csum,
-                  unsigned long long *win, int32_t *match, uint8_t *keep, float *colour, uint8_t *keep_new,
-                  float *colour_new, hipStream_t st);
+                  int64_t capacity, float tau_d, float kappa, const MergeBufs &mb, uint8_t *keep, float *colour,
+                  float *mean_out, uint8_t *keep_new, float *colour_new, float *mean_new, hipStream_t st);
 void launch_downsample(const float *src, int W, int H, int n, float *dst, hipStream_t st);
 void launch_freq_schedule(const float *x_gt, const float *x_gt_level, const float *x_render, int F, float tau_f,
                           int32_t *levels, const float *u, int n_picks, float *r, float *rp, int32_t *picks,

@@ -846,10 +846,10 @@ gsr_status gsr_log_insert(gsr_ctx *c, const gsr_camera *cams, const float *gt, c
 }
 
 // Workspace of gsr_merge: per pixel of the largest view the slot, the group
-// count, colour sums (3 x 64 bit) and the 64-bit winner key; per Gaussian the
-// matched pixel.
+// count, colour sums (3 x 64 bit), the distance sum and the 64-bit winner
+// key; per Gaussian the matched pixel.
 struct MergeLayout {
-  size_t slot, cnt, csum, win, match, bytes;
+  size_t slot, cnt, csum, dsum, win, match, bytes;
 };
 
 MergeLayout merge_layout(const gsr_ctx *c, int64_t n) {
@@ -859,7 +859,8 @@ MergeLayout merge_layout(const gsr_ctx *c, int64_t n) {
   L.slot = 0;
   L.cnt = align_up(px * 4);
   L.csum = L.cnt + align_up(px * 4);
-  L.win = L.csum + align_up(px * 24);
+  L.dsum = L.csum + align_up(px * 24);
+  L.win = L.dsum + align_up(px * 8);
   L.match = L.win + align_up(px * 8);
   L.bytes = L.match + align_up((size_t)std::max<int64_t>(n, 1) * 4);
   return L;
@@ -893,11 +894,13 @@ gsr_status gsr_merge(gsr_ctx *c, const gsr_gaussians *g, int32_t view, const gsr
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   if (ws_bytes < L.bytes) return fail(c, GSR_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
   char *b = static_cast<char *>(ws);
+  const MergeBufs mb{reinterpret_cast<int32_t *>(b + L.slot), reinterpret_cast<uint32_t *>(b + L.cnt),
+                     reinterpret_cast<unsigned long long *>(b + L.csum),
+                     reinterpret_cast<unsigned long long *>(b + L.dsum),
+                     reinterpret_cast<unsigned long long *>(b + L.win), reinterpret_cast<int32_t *>(b + L.match)};
   launch_merge(gauss_ptrs(g), g->n, reinterpret_cast<const Cam *>(cams), view, c->views[(size_t)view], gt, p_gt,
-               samples->pix, samples->mean, samples->count, samples->capacity, cfg->tau_d, cfg->kappa,
-               reinterpret_cast<int32_t *>(b + L.slot), reinterpret_cast<uint32_t *>(b + L.cnt),
-               reinterpret_cast<unsigned long long *>(b + L.csum), reinterpret_cast<unsigned long long *>(b + L.win),
-               reinterpret_cast<int32_t *>(b + L.match), out->keep, out->colour, out->keep_new, out->colour_new,
+               samples->pix, samples->mean, samples->count, samples->capacity, cfg->tau_d, cfg->kappa, mb, out->keep,
+               out->colour, out->mean, out->keep_new, out->colour_new, out->mean_new,
                static_cast<hipStream_t>(stream));
   GSR_HIP(c, hipGetLastError());
   return GSR_OK;

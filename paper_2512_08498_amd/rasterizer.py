@@ -384,10 +384,13 @@ class Rasterizer:
         """Merge the existing Gaussians (dict with mean [3, n], log_scale
         [3, n], sh [K, 3, n]) with the samples of ``view`` from ``ins`` (a
         log_insert result): returns dict(keep [n] uint8, colour [3, n],
-        keep_new [capacity] uint8, colour_new [capacity, 3]) (see gsr_merge).
-        New result tensors have keep_new and colour_new zeroed; ``out`` (a
-        dict of that form, e.g. an earlier result) is written in place
-        instead, where the entries of other views' samples keep their values."""
+        mean [3, n], keep_new [capacity] uint8, colour_new [capacity, 3],
+        mean_new [capacity, 3]) (see gsr_merge; the means are the centres
+        after the depth re-alignment).  New result tensors have keep_new,
+        colour_new and mean_new zeroed; ``out`` (a dict of that form, e.g. an
+        earlier result; "mean" and "mean_new" may be left out) is written in
+        place instead, where the entries of other views' samples keep their
+        values."""
         n = existing["mean"].shape[1]
         k = existing["sh"].shape[0]
         deg = int(round(k ** 0.5)) - 1
@@ -407,15 +410,18 @@ class Rasterizer:
         ws = getattr(self, "_merge_ws", None)
         if ws is None or ws.numel() < int(nb.value):
             ws = self._merge_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        shapes = (("keep", torch.uint8, (max(n, 1),)), ("colour", torch.float32, (3, max(n, 1))),
+                  ("mean", torch.float32, (3, max(n, 1))), ("keep_new", torch.uint8, (cap,)),
+                  ("colour_new", torch.float32, (cap, 3)), ("mean_new", torch.float32, (cap, 3)))
         if out is None:
-            res = dict(keep=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
-                       colour=torch.empty(3, max(n, 1), dtype=torch.float32, device=self.device),
-                       keep_new=torch.zeros(cap, dtype=torch.uint8, device=self.device),
-                       colour_new=torch.zeros(cap, 3, dtype=torch.float32, device=self.device))
+            res = {name: (torch.zeros if name.endswith("_new") else torch.empty)(shape, dtype=dtype,
+                                                                                 device=self.device)
+                   for name, dtype, shape in shapes}
         else:
             res = out
-            for name, dtype, shape in (("keep", torch.uint8, (max(n, 1),)), ("colour", torch.float32, (3, max(n, 1))),
-                                       ("keep_new", torch.uint8, (cap,)), ("colour_new", torch.float32, (cap, 3))):
+            for name, dtype, shape in shapes:
+                if name not in res and name in ("mean", "mean_new"):
+                    continue
                 t = res[name]
                 if t.dtype != dtype or not t.is_contiguous() or t.device != self.device or tuple(t.shape) != shape:
                     raise ValueError(f"out[{name}]: expected contiguous {dtype} {shape} on {self.device}, got "
@@ -425,7 +431,8 @@ class Rasterizer:
         so = L.InsertOut(ins["pix"].data_ptr(), ins["scale"].data_ptr(), ins["mean"].data_ptr(),
                          ins["count"].data_ptr(), cap)
         mo = L.MergeOut(res["keep"].data_ptr(), res["colour"].data_ptr(), res["keep_new"].data_ptr(),
-                        res["colour_new"].data_ptr())
+                        res["colour_new"].data_ptr(), res["mean"].data_ptr() if "mean" in res else None,
+                        res["mean_new"].data_ptr() if "mean_new" in res else None)
         cams = cams_dev if cams_dev is not None else self.cams_dev
         self._check(self.lib.gsr_merge(self.ctx, C.byref(g), int(view), _vp(cams), _vp(gt), _vp(ins["p_gt"]),
                                        C.byref(so), C.byref(L.MergeConfig(float(tau_d), float(kappa))), C.byref(mo),

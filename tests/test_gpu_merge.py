@@ -47,8 +47,15 @@ def _compare(res, ref, n, k):
     ok_g, ok_n = ~ref["ambiguous_g"], ~ref["ambiguous_new"]
     assert np.array_equal(keep[ok_g], ref["keep"][ok_g])
     assert np.array_equal(keep_new[ok_n], ref["keep_new"][ok_n])
-    assert np.abs(colour[ok_g] - ref["colour"][ok_g]).max() <= 1e-6
-    assert np.abs(colour_new[ok_n] - ref["colour_new"][ok_n]).max() <= 1e-6
+    assert np.abs(colour[ok_g] - ref["colour"][ok_g]).max(initial=0.0) <= 1e-6
+    assert np.abs(colour_new[ok_n] - ref["colour_new"][ok_n]).max(initial=0.0) <= 1e-6
+    if "mean" in res:
+        # re-aligned centres: the double-precision result rounded to float32
+        mean = res["mean"][:, :n].cpu().numpy().astype(np.float64)
+        mean_new = res["mean_new"][:k].cpu().numpy().astype(np.float64)
+        rm, rmn = ref["mean"][:, ok_g], ref["mean_new"][ok_n]
+        assert (np.abs(mean[:, ok_g] - rm) <= 1e-6 * np.maximum(1.0, np.abs(rm))).all()
+        assert (np.abs(mean_new[ok_n] - rmn) <= 1e-6 * np.maximum(1.0, np.abs(rmn))).all()
     log(f"  {int((ref['match'] >= 0).sum())} matched Gaussians, {int((~ref['keep']).sum())} removed, "
         f"{int((~ref['keep_new']).sum())} of {k} samples dropped; ambiguous {int(ref['ambiguous_g'].sum())} "
         f"Gaussians, {int(ref['ambiguous_new'].sum())} samples")
@@ -74,8 +81,13 @@ def _small_view_case(seed):
     centres = ((xc - tf) @ Rf).astype(np.float32)
     mean = np.stack([rng.uniform(-2, 2, N), rng.uniform(-1.5, 1.5, N), rng.uniform(-1, 8, N)])
     for g in range(0, N, 2):
+        # near a sample's depth, projected within 0.7 px of its pixel centre
+        # (so across pixel borders, where the bilinear match differs from the
+        # containing pixel)
         k = rng.integers(0, K)
-        mean[:, g] = (xc[k] * rng.uniform(0.92, 1.08) - tf) @ Rf
+        zz = xc[k, 2] * rng.uniform(0.92, 1.08)
+        uu, vv = u[k] + rng.uniform(-0.7, 0.7), v[k] + rng.uniform(-0.7, 0.7)
+        mean[:, g] = (np.array([zz * (uu - 24) / 60, zz * (vv - 16) / 60, zz]) - tf) @ Rf
     mean = mean.astype(np.float32)
     ls = rng.normal(-3.0, 0.6, (3, N)).astype(np.float32)
     sh = rng.normal(0, 1, (1, 3, N)).astype(np.float32)
@@ -178,3 +190,51 @@ def test_merge_without_samples():
     colour = res["colour"][:, :N].cpu().numpy().astype(np.float64).T
     assert np.abs(colour - ref["colour"]).max() <= 1e-6
     assert not res["keep_new"].any()
+
+
+def test_merge_rig_view_with_a_tight_depth_bound():
+    """The rig's 1600x900 view 0 with the 1M-Gaussian scene as the existing
+    set and tau_d = 0.5 m: each sample's centre is placed on its pixel's ray
+    at the distance of a scene Gaussian that projects near it, plus N(0, 0.4 m),
+    so the depth bound accepts some correspondences and rejects others at
+    full scale."""
+    scene, cams = make_config(3)
+    view = 0
+    cam = cams[view]
+    rast = Rasterizer(cams, 1, 0)
+    gts, rds, depths = make_insert_inputs(rast.sizes, 61)
+    gt_flat = np.concatenate([g.reshape(-1) for g in gts])
+    o = insert(gts[view], rds[view], depths[view], cam)
+    W, H = rast.sizes[view]
+    # distances of scene Gaussians by the pixel their projection falls in
+    R = np.asarray(cam.R, np.float64)
+    xc = R @ scene.mean.astype(np.float64) + np.asarray(cam.t, np.float64)[:, None]
+    front = xc[2] > 0.2
+    u = cam.fx * xc[0] / np.where(front, xc[2], 1) + cam.cx
+    v = cam.fy * xc[1] / np.where(front, xc[2], 1) + cam.cy
+    ok = front & (u >= 0) & (u < W) & (v >= 0) & (v < H)
+    pix_g = (np.floor(v[ok]).astype(np.int64) * W + np.floor(u[ok]).astype(np.int64))
+    dist_at = np.full(W * H, np.nan)
+    dist_at[pix_g] = np.linalg.norm(xc[:, ok], axis=0)
+    rng = np.random.default_rng(65)
+    pix = o["pix"]
+    d = dist_at[pix]
+    has = np.isfinite(d)
+    assert has.sum() > 1000
+    d = np.where(has, d + rng.normal(0, 0.4, len(pix)), rng.uniform(5, 40, len(pix)))
+    ray = np.stack([(pix % W + 0.5 - cam.cx) / cam.fx, (pix // W + 0.5 - cam.cy) / cam.fy, np.ones(len(pix))], 1)
+    xs = ray / np.linalg.norm(ray, axis=1, keepdims=True) * d[:, None]
+    centres = ((xs - np.asarray(cam.t, np.float64)) @ R).astype(np.float32)
+    host, dev = _samples_for(rast, cams, view, pix, centres, gt_flat)
+    p_full = np.zeros(rast.total_px, np.float32)
+    p_full[rast.pix_off[view]:rast.pix_off[view + 1]] = o["p_gt"].reshape(-1)
+    dev["p_gt"] = torch.from_numpy(p_full).cuda()
+    ex = {k: torch.from_numpy(np.ascontiguousarray(v_)).cuda() for k, v_ in scene.arrays().items()}
+    res = rast.merge(ex, view, torch.from_numpy(gt_flat).cuda(), dev, tau_d=0.5)
+    torch.cuda.synchronize()
+    ref = merge(scene.mean, scene.log_scale, scene.sh[0], cam, host, o["p_gt"].astype(np.float32), tau_d=0.5)
+    loose = merge(scene.mean, scene.log_scale, scene.sh[0], cam, host, o["p_gt"].astype(np.float32), tau_d=50.0)
+    rejected = int(((loose["match"] >= 0) & (ref["match"] < 0)).sum())
+    log(f"tight tau_d: {len(pix)} samples, {rejected} correspondences rejected by depth")
+    assert rejected > 100
+    assert _compare(res, ref, scene.n, len(pix)) > 100
