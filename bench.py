@@ -12,12 +12,17 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   roofline      achieved vs peak of the dominant kernel, its duration taken
                 from HIP events recorded around it on the library's stream
                 during an eager pass of the same steps
-  cpu_baseline  the FP64 CPU oracle timed on a bounded pixel sample
+  cpu_baseline  the FP64 CPU oracle timed on a bounded pixel sample, one
+                single-threaded worker process per host core (at most 15)
   step_ms_spread  p10 / median / p90 of 30 single replays (HIP events)
   hbm_copy_gbs  achievable HBM bandwidth (the library's streaming copy of
                 1 GiB), and the step's algorithmic bytes as a fraction of it
-  per_view      the same step issued as plain per-view launches (no batching,
-                no graph), for comparison
+  per_view      batched against plain per-view launches, both arranged the
+                same way (forward with the fused loss, backward to dense
+                gradients, one Adam step) and graph-captured (per-view also
+                eager)
+  window        the same comparison, and the fused step, on the 40-view
+                uneven keyframe window (2M Gaussians)
   pose          the same step with each view's camera-pose gradient and its
                 rig chain (central pose per frame, relative transform per
                 camera) added, as a second captured graph
@@ -127,21 +132,49 @@ def recorded_traffic(kernel, workload):
     return float(m_b.group(1))
 
 
-def cpu_baseline(scene, cams, targets, total_px, budget_s=15.0, win=32, seed=3003):
-    """The oracle (forward + gradients) on random win x win pixel windows."""
+# --- CPU baseline: the oracle on pixel windows, one single-threaded worker
+# process per host core of the GPU's share (at most 15 besides this one) -----
+_ORACLE_STATE = {}
+
+
+def _oracle_worker_init():
+    """Each worker runs single-threaded (NumPy's and torch's pools at one
+    thread), so the process count is the core count."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _oracle_windows(task):
+    """Worker: forward + FP64 autograd backward of the oracle on random
+    win x win windows of the workload for budget_s seconds (scene generation
+    not timed).  Returns (pixels, windows, seconds)."""
+    config, scale, worker, budget_s, win, seed = task
     import torch
 
+    torch.set_num_threads(1)
     from oracle.grad64 import grad64
-    from oracle.render64 import render_view
     from oracle.project64 import to_params64
+    from oracle.render64 import render_view
+    from workloads import make_config, make_target
 
+    key = (config, scale)
+    if key not in _ORACLE_STATE:
+        scene, cams = make_config(config, scale)
+        targets = make_target(config, cams)
+        _ORACLE_STATE[key] = (scene, cams, targets, to_params64(scene.arrays()),
+                              sum(c.width * c.height for c in cams))
+    scene, cams, targets, p64, total_px = _ORACLE_STATE[key]
     arrays = scene.arrays()
-    p64 = to_params64(arrays)
-    rng = np.random.default_rng(seed)
-    done_px, n_win = 0, 0
+    rng = np.random.default_rng(seed + 7919 * worker)
+    done_px = n_win = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and n_win < 64:
-        v = n_win % len(cams)
+    while time.perf_counter() - t0 < budget_s:
+        v = (worker + n_win) % len(cams)
         c = cams[v]
         x0 = int(rng.integers(0, c.width - win + 1))
         y0 = int(rng.integers(0, c.height - win + 1))
@@ -153,12 +186,161 @@ def cpu_baseline(scene, cams, targets, total_px, budget_s=15.0, win=32, seed=300
         grad64(scene, [c], [cot], windows=[w])
         done_px += win * win
         n_win += 1
-    dt = time.perf_counter() - t0
-    mpix = done_px / dt / 1e6
-    return {"value": mpix * 1e6 / total_px, "unit": "it/s", "mpix_per_s": mpix, "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n_win} windows of {win}x{win} px across the views (forward + FP64 autograd backward), "
-                      f"{dt:.1f} s; rate scaled to one full iteration of {total_px} px"}
+    return done_px, n_win, time.perf_counter() - t0
+
+
+def oracle_workers():
+    """Worker count: the host cores this process may use, at most 15, so
+    that with this process the run stays within one GPU's share of the host
+    (16 processes, which the GPU hosts enforce per process tree)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(15, avail))
+
+
+def start_oracle_pool(n):
+    """The worker pool, forked before this process touches the GPU."""
+    import multiprocessing as mp
+
+    return mp.get_context("fork").Pool(n, initializer=_oracle_worker_init)
+
+
+def cpu_baseline(pool, n_workers, config, scale, total_px, budget_s=15.0, win=32, seed=3003):
+    """The oracle timed on all workers at once: each renders and
+    differentiates random windows for budget_s seconds; the rate is the
+    pixels done over the wall time of the slowest worker, scaled to one full
+    iteration of total_px pixels."""
+    res = pool.map(_oracle_windows, [(config, scale, w, budget_s, win, seed) for w in range(n_workers)])
+    px = sum(r[0] for r in res)
+    n_win = sum(r[1] for r in res)
+    wall = max(r[2] for r in res)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    mpix = px / wall / 1e6
+    return {"value": mpix * 1e6 / total_px, "unit": "it/s", "mpix_per_s": mpix, "cores": n_workers,
+            "kind": "oracle", "host_cpus": os.cpu_count(), "cpu_model": model, "extrapolated": True,
+            "sample": f"{n_win} windows of {win}x{win} px across the views (FP64 forward + autograd backward), "
+                      f"{n_workers} single-threaded worker processes for {wall:.1f} s; rate extrapolated "
+                      f"linearly to one full iteration of {total_px} px"}
+
+
+def batching_comparison(scene, cams, target, params, rast, dev, steps, warmup, replayable, timed, ms_fused):
+    """Batched launch against plain per-view launches with the same loss and
+    optimiser arrangement: each view's forward with the fused L1 loss, its
+    dL/dC rescaled from the view's mean to the batch mean (one torch
+    multiply), its backward accumulated into dense gradients, then one Adam
+    step; and the batched step arranged the same way (forward with the
+    loss, backward to gradients, Adam).  Both are timed as captured graphs;
+    the per-view step also eagerly."""
+    import torch
+
+    from paper_2512_08498_amd import FusedAdam, Rasterizer
+
+    tun = rast.tuning()
+    grads = {k: torch.zeros_like(v) for k, v in params.items()}
+    opt2 = FusedAdam(rast, params)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    out = rast.new_fwd_out()
+    dl = torch.empty_like(out["image"])
+
+    def step_b():
+        rast.forward_l1(params, target, out=out, loss_out=loss, dl_out=dl, check=False)
+        rast.backward(params, out, dl, grads=grads)
+        opt2.apply(grads)
+
+    run_b = replayable(step_b, [rast])
+    b_ms = timed(run_b, steps) / steps * 1e3
+
+    rs = []
+    for c in cams:
+        r = Rasterizer([c], scene.n, scene.sh_degree, tile_size=tun["tile_size"], long_list=tun["long_list"],
+                       device=dev, capacity_records=max(scene.n // 4, 65536), capacity_pairs=max(scene.n, 262144))
+        r.forward(params)
+        rr, pp, _ = r.required_capacity()
+        r._plan(int(rr * 1.5) + 4096, int(pp * 1.5) + 65536)
+        rs.append(r)
+    outs = [r.new_fwd_out() for r in rs]
+    tv = [target[3 * rast.pix_off[v]:3 * rast.pix_off[v + 1]] for v in range(len(cams))]
+    dls = [torch.empty_like(o["image"]) for o in outs]
+    frac = [(rast.pix_off[v + 1] - rast.pix_off[v]) / rast.total_px for v in range(len(cams))]
+
+    def step_pv():
+        for v, r in enumerate(rs):
+            r.forward_l1(params, tv[v], out=outs[v], loss_out=loss, dl_out=dls[v], check=False)
+            dls[v].mul_(frac[v])
+            r.backward(params, outs[v], dls[v], grads=grads, accumulate=v > 0)
+        opt2.apply(grads)
+
+    n_pv = max(5, steps // 4)
+    pv_eager_ms = timed(step_pv, n_pv) / n_pv * 1e3
+    for r in rs:
+        r.check()
+    run_pv = replayable(step_pv, rs)
+    pv_ms = timed(run_pv, n_pv) / n_pv * 1e3
+    for r in rs:
+        r.check()
+    del rs, outs, dls
+    return {"batched_it_s": 1e3 / b_ms, "batched_ms": b_ms, "per_view_it_s": 1e3 / pv_ms, "per_view_ms": pv_ms,
+            "per_view_eager_it_s": 1e3 / pv_eager_ms, "per_view_eager_ms": pv_eager_ms,
+            "speedup_batching": pv_ms / b_ms, "speedup_headline_step": pv_ms / ms_fused,
+            "arrangement": "forward with fused L1, backward to dense gradients, one Adam step; per-view dL/dC "
+                           "rescaled to the batch mean; both legs graph-captured (per-view also eager)",
+            "tuning": tun}
+
+
+def window_leg(args, dev, replayable, timed):
+    """The uneven keyframe window (8 rig frames x 5 cameras at mixed
+    resolutions, 2M Gaussians): the fused training step, autotuned and
+    graph-captured, and the batched vs per-view comparison on it."""
+    import torch
+
+    from paper_2512_08498_amd import FusedAdam, Rasterizer
+    from workloads import config_names, make_config, make_target
+
+    t0 = time.perf_counter()
+    scene, cams = make_config(4, args.scale)
+    targets = make_target(4, cams)
+    params = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.arrays().items()}
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in targets])).to(dev)
+    del targets
+    r = Rasterizer(cams, scene.n, scene.sh_degree, device=dev, capacity_records=len(cams) * scene.n // 4,
+                   capacity_pairs=len(cams) * scene.n)
+    r.forward(params)
+    rec, pairs, _ = r.required_capacity()
+    r._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
+    tuning = r.autotune(params, repeats=3)
+    r.forward(params)
+    rec, pairs, _ = r.required_capacity()
+    r._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
+    log(f"window: {scene.n} Gaussians, {len(cams)} views, {r.total_px} px, tuning {tuning} "
+        f"({time.perf_counter() - t0:.1f} s set-up)")
+    opt = FusedAdam(r, params)
+    out = r.new_fwd_out()
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    dl = torch.empty_like(out["image"])
+
+    def step():
+        r.forward_l1(params, target, out=out, loss_out=loss, dl_out=dl, check=False)
+        r.backward_adam(params, out, dl, opt)
+
+    run = replayable(step, [r])
+    ms = timed(run, args.steps) / args.steps * 1e3
+    r.check()
+    cmp = batching_comparison(scene, cams, target, params, r, dev, args.steps, args.warmup, replayable, timed, ms)
+    res = {"workload": config_names()[4], "views": len(cams), "gaussians": scene.n, "pixels": r.total_px,
+           "it_s": 1e3 / ms, "ms_per_step": ms, "mpix_per_s": r.total_px / ms / 1e3, **cmp}
+    log(f"window: {res['it_s']:.2f} it/s fused; batched (same arrangement) {cmp['batched_it_s']:.2f} it/s, "
+        f"per-view {cmp['per_view_it_s']:.2f} it/s graph ({cmp['per_view_eager_it_s']:.2f} eager): batching "
+        f"{cmp['speedup_batching']:.2f}x")
+    del r, opt, out, dl, params, target
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -172,6 +354,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-window", action="store_true",
+                    help="skip the batched vs per-view comparison on the 40-view uneven keyframe window")
     ap.add_argument("--no-pose", action="store_true")
     ap.add_argument("--no-freq", action="store_true")
     ap.add_argument("--no-insert", action="store_true")
@@ -185,6 +369,13 @@ def main():
         print("bench.py measures one GPU only: the rasterizer path is built and timed on a single GPU (sharding "
               "by view across GPUs is a design note, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's worker processes are forked now, before this process
+    # touches the GPU; they stay idle until the GPU timing is done
+    pool, n_workers = None, 0
+    if not args.no_cpu_baseline and not args.copy_calibration:
+        n_workers = oracle_workers()
+        pool = start_oracle_pool(n_workers)
 
     import torch
 
@@ -235,9 +426,10 @@ def main():
         rast.forward_l1(params, target, out=out, loss_out=loss, dl_out=dl, check=False)
         rast.backward_adam(params, out, dl, opt)
 
-    def replayable(fn):
+    def replayable(fn, rasts=None):
         fn()
-        rast.check()
+        for r in (rasts if rasts is not None else [rast]):
+            r.check()
         if args.no_graph:
             return fn
         side = torch.cuda.Stream(dev)
@@ -352,40 +544,11 @@ def main():
 
     per_view = None
     if not args.no_per_view and len(cams) > 1:
-        ll = rast.tuning()["long_list"]
-        rs = [Rasterizer([c], scene.n, scene.sh_degree, tile_size=rast.tile_size, long_list=ll, device=dev,
-                         capacity_records=max(scene.n // 4, 65536), capacity_pairs=max(scene.n, 262144))
-              for c in cams]
-        outs = []
-        for r in rs:
-            o = r.forward(params)
-            rr, pp, _ = r.required_capacity()
-            r._plan(int(rr * 1.5) + 4096, int(pp * 1.5) + 65536)
-            outs.append(r.new_fwd_out())
-        grads = {k: torch.zeros_like(v) for k, v in params.items()}
-        tv = [target[3 * rast.pix_off[v]:3 * rast.pix_off[v + 1]] for v in range(len(cams))]
-        dls = [torch.empty_like(o["image"]) for o in outs]
-        opt2 = FusedAdam(rast, params)
-
-        def step_pv():
-            for v, r in enumerate(rs):
-                r.forward(params, out=outs[v], check=False)
-                r.l1_loss(outs[v]["image"], tv[v], loss, dls[v])
-                dls[v].mul_(1.0 / len(cams))
-                r.backward(params, outs[v], dls[v], grads=grads, accumulate=v > 0)
-            opt2.apply(grads)
-
-        for _ in range(3):
-            step_pv()
-        torch.cuda.synchronize(dev)
-        n_pv = max(5, args.steps // 4)
-        t1 = time.perf_counter()
-        for _ in range(n_pv):
-            step_pv()
-        torch.cuda.synchronize(dev)
-        pv_ms = (time.perf_counter() - t1) / n_pv * 1e3
-        per_view = {"it_s": 1e3 / pv_ms, "ms_per_step": pv_ms, "speedup_batched": pv_ms / ms}
-        log(f"per-view plain launches: {1e3 / pv_ms:.2f} it/s")
+        per_view = batching_comparison(scene, cams, target, params, rast, dev, args.steps, args.warmup, replayable,
+                                       timed, ms)
+        log(f"batched (same arrangement) {per_view['batched_it_s']:.2f} it/s, per-view plain launches "
+            f"{per_view['per_view_it_s']:.2f} it/s as a graph ({per_view['per_view_eager_it_s']:.2f} eager): "
+            f"batching {per_view['speedup_batching']:.2f}x")
 
     pose = None
     if not args.no_pose:
@@ -502,10 +665,17 @@ def main():
         log(f"merge of {scene.n} Gaussians with view 0's samples: {m_ms:.3f} ms "
             f"({ins['merge']['hbm_frac']:.1%} of HBM peak)")
 
+    window = None
+    if not args.no_window and not args.no_per_view and args.config != 4:
+        window = window_leg(args, dev, replayable, timed)
+
     cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a pixel sample")
-        cpu = cpu_baseline(scene, cams, targets, total_px, budget_s=args.cpu_budget)
+    if pool is not None:
+        log(f"timing the CPU oracle on pixel windows ({n_workers} worker processes)")
+        cpu = cpu_baseline(pool, n_workers, args.config, args.scale, total_px, budget_s=args.cpu_budget)
+        pool.close()
+        pool.join()
+        log(f"oracle: {cpu['mpix_per_s']:.5f} Mpix/s on {n_workers} cores")
 
     res = {
         "metric": METRIC,
@@ -540,6 +710,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_view": per_view,
+        "window": window,
         "pose": pose,
         "freq": freq,
         "insert": ins,
