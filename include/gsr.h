@@ -143,6 +143,26 @@ gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_ca
                               int32_t n_views, void *workspace, size_t workspace_bytes,
                               const gsr_fwd_out *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gsr_render_forward with its workspace in the library's own device scratch
+ * instead of a caller buffer -- a fixed array of GSR_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), one per GPU, held from the first gsr_create on that GPU until
+ * the process ends.  The call allocates nothing and enqueues only; the
+ * caller still passes the inputs and the outputs (as for gsr_render_forward,
+ * whose outputs it reproduces bit for bit).  The context's plan must need a
+ * workspace of at most GSR_NOALLOC_SCRATCH_BYTES (gsr_plan's
+ * workspace_bytes), else GSR_ERR_CAPACITY; the current device must be the
+ * one the context was created on, else GSR_ERR_INVALID_ARG.  Every context
+ * on a GPU shares that GPU's scratch, which keeps the last call's contents
+ * (the forward clears what it needs): calls that may overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller, and only the last forward's state is there for gsr_check and
+ * gsr_required_capacity, which read it when passed workspace = NULL.     */
+#define GSR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gsr_status gsr_render_forward_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                                      int32_t n_views, const gsr_fwd_out *out, void *stream);
+
 /* L1 photometric loss over n_elems image values (all views, channels, pixels):
  * loss = sum |image - target| / n_elems, written to loss_out (DEVICE, 1
  * float); dL_dimage[i] = sign(image[i] - target[i]) / n_elems.  Deterministic
@@ -233,11 +253,13 @@ gsr_status gsr_count_evaluations(gsr_ctx *ctx, void *workspace, const gsr_fwd_ou
 gsr_status gsr_copy_bytes(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Synchronise `stream`, then report GSR_ERR_CAPACITY if the last forward ran
- * out of record or pair capacity, else GSR_OK.                              */
+ * out of record or pair capacity, else GSR_OK.  workspace = NULL reads the
+ * no-alloc scratch of the context's GPU (after gsr_render_forward_noalloc).  */
 gsr_status gsr_check(gsr_ctx *ctx, void *workspace, void *stream);
 
 /* Synchronise `stream` and read the record and pair counts the last forward
- * needed (valid also after a capacity overflow), and the total tile count.  */
+ * needed (valid also after a capacity overflow), and the total tile count.
+ * workspace = NULL: the no-alloc scratch, as for gsr_check.                 */
 gsr_status gsr_required_capacity(gsr_ctx *ctx, void *workspace, int64_t *records, int64_t *pairs,
                                  int64_t *tiles, void *stream);
 

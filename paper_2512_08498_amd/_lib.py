@@ -84,6 +84,7 @@ _SIGS = {
     "gsr_render_forward": [P, C.POINTER(Gaussians), P, C.c_int32, P, C.c_size_t, C.POINTER(FwdOut), P],
     "gsr_l1_loss": [P, P, P, C.c_int64, P, P, P],
     "gsr_render_forward_l1": [P, C.POINTER(Gaussians), P, C.c_int32, P, C.c_size_t, C.POINTER(FwdOut), P, P, P, P],
+    "gsr_render_forward_noalloc": [P, C.POINTER(Gaussians), P, C.c_int32, C.POINTER(FwdOut), P],
     "gsr_render_backward": [P, C.POINTER(Gaussians), P, C.c_int32, P, C.c_size_t, C.POINTER(FwdOut), P,
                             C.POINTER(Grads), C.c_int32, P],
     "gsr_adam_step": [P, C.POINTER(Grads), C.POINTER(Grads), C.POINTER(Moments), C.POINTER(Moments),

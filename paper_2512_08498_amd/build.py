@@ -30,6 +30,7 @@ SOURCES = [
     "freq.hip",
     "insert.hip",
     "merge.hip",
+    "scratch.hip",
     "runtime.cpp",
     "autotune.cpp",
 ]

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "gsr.h"
 
 namespace gsr {
 
@@ -85,6 +86,11 @@ void launch_log_insert(const ViewInfo *views_d, int n_views, uint32_t n_tiles, i
                        float *p_gt, float *p_rd, uint8_t *mask, uint32_t *counts, uint32_t *offsets,
                        uint32_t *total, uint32_t *out_pix, float *out_scale, float *out_mean, int64_t capacity,
                        hipStream_t st);
+// Device scratch of gsr_render_forward_noalloc (scratch.hip): its size, and
+// the address of a device's copy (looked up once per device).
+constexpr size_t kScratchBytes = GSR_NOALLOC_SCRATCH_BYTES;
+hipError_t scratch_address(int device, void **out);
+
 // Per-pixel (of the view) and per-Gaussian scratch of the merge.
 struct MergeBufs {
   int32_t *slot;

@@ -32,6 +32,9 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct gsr_ctx {
   std::string err;
   bool planned = false;
+  // device current at gsr_create, and its copy of the no-alloc scratch
+  int device = 0;
+  void *scratch = nullptr;
   int32_t n_views = 0;
   int64_t n = 0;
   int32_t sh_degree = 0;
@@ -254,7 +257,8 @@ gsr_status gsr_create(gsr_ctx **out) {
   if (!out) return GSR_ERR_INVALID_ARG;
   *out = nullptr;
   gsr_ctx *c = new gsr_ctx();
-  if (hipMalloc(&c->loss_partials, kLossBlocks * sizeof(float)) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess || scratch_address(c->device, &c->scratch) != hipSuccess ||
+      hipMalloc(&c->loss_partials, kLossBlocks * sizeof(float)) != hipSuccess) {
     gsr_destroy(c);
     return GSR_ERR_HIP;
   }
@@ -378,6 +382,23 @@ static gsr_status forward_common(gsr_ctx *c, const gsr_gaussians *g, const gsr_c
 gsr_status gsr_render_forward(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
                               void *ws_base, size_t ws_bytes, const gsr_fwd_out *out, void *stream) {
   return forward_common(c, g, cams, n_views, ws_base, ws_bytes, out, LossArgs{nullptr, nullptr, nullptr, 0.0f},
+                        stream);
+}
+
+gsr_status gsr_render_forward_noalloc(gsr_ctx *c, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                      const gsr_fwd_out *out, void *stream) {
+  if (!c) return GSR_ERR_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
+  if (c->lay.total > kScratchBytes)
+    return fail(c, GSR_ERR_CAPACITY, "the plan needs a workspace of %zu bytes, above the %zu bytes of the library's "
+                "no-alloc scratch; use gsr_render_forward with a caller workspace", c->lay.total, kScratchBytes);
+  int dev = -1;
+  GSR_HIP(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, GSR_ERR_INVALID_ARG, "current device %d is not the context's device %d", dev, c->device);
+  // the forward's first kernel clears the counters and tile counts it needs
+  // at zero, so what an earlier call left in the scratch does not matter
+  return forward_common(c, g, cams, n_views, c->scratch, kScratchBytes, out, LossArgs{nullptr, nullptr, nullptr, 0.0f},
                         stream);
 }
 
@@ -576,7 +597,10 @@ gsr_status gsr_copy_bytes(void *dst, const void *src, size_t bytes, void *stream
 static gsr_status read_scalars(gsr_ctx *c, void *ws_base, void *stream, uint32_t out[kNumScalars]) {
   if (!c) return GSR_ERR_INVALID_ARG;
   if (!c->planned) return fail(c, GSR_ERR_NOT_PLANNED, "gsr_plan has not been called");
-  if (!ws_base) return fail(c, GSR_ERR_INVALID_ARG, "workspace is NULL");
+  if (!ws_base) {  // the no-alloc forward's scratch
+    if (c->lay.total > kScratchBytes) return fail(c, GSR_ERR_INVALID_ARG, "workspace is NULL");
+    ws_base = c->scratch;
+  }
   GSR_HIP(c, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
   GSR_HIP(c, hipMemcpy(out, static_cast<char *>(ws_base) + c->lay.scalars, kNumScalars * 4, hipMemcpyDeviceToHost));
   return GSR_OK;

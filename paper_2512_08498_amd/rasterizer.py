@@ -200,6 +200,25 @@ class Rasterizer:
             self._check(st)
         return out
 
+    def forward_noalloc(self, params, out=None, cams_dev=None):
+        """forward() through gsr_render_forward_noalloc: the workspace is the
+        library's per-GPU device scratch (the plan must fit in
+        GSR_NOALLOC_SCRATCH_BYTES), so the call allocates nothing given
+        ``out``.  No capacity re-plan: check_noalloc() reports an overflow.
+        The backward cannot follow it (its binning state is not in this
+        rasterizer's workspace)."""
+        out = out if out is not None else self.new_fwd_out()
+        g = self._gaussians(params)
+        cams = cams_dev if cams_dev is not None else self.cams_dev
+        self.generation += 1
+        self._check(self.lib.gsr_render_forward_noalloc(self.ctx, C.byref(g), _vp(cams), self.views,
+                                                        C.byref(self._fwd_struct(out)), self.stream()))
+        return out
+
+    def check_noalloc(self):
+        """gsr_check of the no-alloc scratch (synchronises)."""
+        self._check(self.lib.gsr_check(self.ctx, None, self.stream()))
+
     def forward_l1(self, params, target, out=None, loss_out=None, dl_out=None, check=True, cams_dev=None):
         """forward() with the L1 loss against ``target`` fused in: returns
         (out, loss [1], dL/dimage)."""
