@@ -74,6 +74,40 @@ __device__ __forceinline__ bool tile_reaches(const float4 box, const float4 p1, 
   return !(fmin > thr + (0.0625f + 0x1p-18f * big));
 }
 
+// Which staged records each 8 x 8 pixel block of the calling thread's wave
+// can composite.  Every pixel mapping of the compositing kernels gives a wave
+// one 8 x 8 block per pixel slot p, lane l at (l & 7, l >> 3) within it, so
+// the block origin is the pixel of the wave's lane 0.  mk[p][c] bit b: the
+// compositing box of batch record 64 c + b (c < NC, 64 c + b < m) meets
+// block p.  Outside that box alpha < 1/255 at every pixel centre (the box is
+// the alpha >= 1/255 region's bounding box, with a margin), so a record
+// whose bit is clear composites nowhere in the block, and within a block the
+// per-pixel alpha test alone decides.  The masks are wave-uniform, so the
+// record loops branch on them in scalar registers and skip records without
+// touching LDS.  Every thread of the group must call this after the batch's
+// payloads p0 (boxes) are in LDS.
+template <int PPT, int NC, class Pix>
+__device__ __forceinline__ void block_masks(const float4 *p0, uint32_t m, int t, float ox, float oy, Pix pix,
+                                            uint64_t (&mk)[PPT][NC]) {
+  float bx[PPT], by[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    int x, y;
+    pix(t & ~(kWave - 1), p, x, y);
+    bx[p] = ox + (float)x;
+    by[p] = oy + (float)y;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const uint32_t j = (uint32_t)(c * kWave + lane_id());
+    const bool live = j < m;
+    const float4 b = p0[live ? j : 0u];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+      mk[p][c] = __ballot(live & (b.x <= bx[p] + 7.0f) & (b.y >= bx[p]) & (b.z <= by[p] + 7.0f) & (b.w >= by[p]));
+  }
+}
+
 // Slot of this thread's record in the compacted batch: the kept records
 // numbered in thread order.  A workgroup (WG) exchanges its NW per-wave
 // counts through wc with one barrier; a single wave needs none.  Returns the

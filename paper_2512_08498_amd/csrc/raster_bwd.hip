@@ -183,74 +183,86 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
     }
     for (uint32_t k = t; k < mc * NW * 9; k += NT) L.g[k] = 0.0f;
     group_sync<WG>();
-    for (int jj = (int)mc - 1; jj >= 0; --jj) {
-      const uint32_t pos = L.pos[jj];
-      const float4 box = L.p0[jj];
-      bool in[PPT];
-      bool any_in = false;
+    // records by 8 x 8 pixel block (wave-uniform bit masks), walked back to
+    // front: a wave visits only the records that can composite in one of its
+    // blocks, and there only the pixels in front of their stored end
+    constexpr int NC = (B + kWave - 1) / kWave;
+    uint64_t mk[PPT][NC];
+    block_masks<PPT, NC>(L.p0, mc, t, ox, oy, pix, mk);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        in[p] = (pos < last[p]) & (fx[p] >= box.x) & (fx[p] <= box.y) & (fy[p] >= box.z) & (fy[p] <= box.w);
-        any_in |= in[p];
-      }
-      // (wave-uniform) records no pixel of the wave touches cost only the tests
-      if (__ballot(any_in) == 0) continue;
-      // With dq = dL/dalpha alpha (dL/dq without the ln 2 of d alpha / dq)
-      // each pixel adds dq u, dq dy, dq u^2, dq u dy and dq dy^2; the record's
-      // constants qa, qb, qc and ln 2 turn the sums into the payload
-      // gradients once, in the epilogue.  The empty asm keeps the zeros
-      // opaque, so the compiler does not re-materialise them on every path
-      // through the per-pixel branches.
-      float a_u = 0.f, a_dy = 0.f, a_qa = 0.f, a_udy = 0.f, a_qc = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f,
-            a_b = 0.f;
-      asm volatile("" : "+v"(a_u), "+v"(a_dy), "+v"(a_qa), "+v"(a_udy), "+v"(a_qc), "+v"(a_o), "+v"(a_r),
-                   "+v"(a_g), "+v"(a_b));
-      bool any = false;
-      if (any_in) {
+    for (int c = NC - 1; c >= 0; --c) {
+      uint64_t rem = 0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) rem |= mk[p][c];
+      while (rem) {
+        const int jb = 63 - __builtin_clzll(rem);
+        rem &= ~(uint64_t(1) << jb);
+        const int jj = c * kWave + jb;
+        const uint32_t pos = L.pos[jj];
+        const float4 box = L.p0[jj];
+        // per 8 x 8 block: skipped (wave-uniform) unless one of its pixels
+        // is in front of its stored end and reaches alpha >= 1/255; then
+        // branch-free: lanes that do not composite take alpha = 0, which
+        // leaves T (rcp(1) = 1), the suffix colours and every sum unchanged
+        // bit for bit.  With dq = dL/dalpha alpha (dL/dq without the ln 2 of
+        // d alpha / dq) each pixel adds dq u, dq dy, dq u^2, dq u dy and
+        // dq dy^2; the record's constants qa, qb, qc and ln 2 turn the sums
+        // into the payload gradients once, in the epilogue.  The empty asm
+        // keeps the zeros opaque, so the compiler does not re-materialise
+        // them on every path.
+        float a_u = 0.f, a_dy = 0.f, a_qa = 0.f, a_udy = 0.f, a_qc = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f,
+              a_b = 0.f;
+        asm volatile("" : "+v"(a_u), "+v"(a_dy), "+v"(a_qa), "+v"(a_udy), "+v"(a_qc), "+v"(a_o), "+v"(a_r),
+                     "+v"(a_g), "+v"(a_b));
+        bool any = false;
         const float4 q1 = L.p1[jj], q2 = L.p2[jj];
         const float cb = L.p3[jj].x;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          if (in[p]) {
-            const float dx = (fx[p] - box.x) - q1.x;
-            const float dy = (fy[p] - box.z) - q1.y;
-            const float u = fmaf(q1.w, dy, dx);
-            const float u2 = u * u, dy2 = dy * dy;
-            const float q = fmaf(q1.z, u2, q2.x * dy2);
-            const float e = __builtin_amdgcn_exp2f(q);
-            const float oe = q2.y * e;
-            const float alpha = fminf(kAlphaMax, oe);
-            if (alpha >= kAlphaMin) {
-              any = true;
-              const float ti = T[p] * __builtin_amdgcn_rcpf(1.0f - alpha);
-              const float w = alpha * ti;
-              a_r = fmaf(g0[p], w, a_r);
-              a_g = fmaf(g1[p], w, a_g);
-              a_b = fmaf(g2[p], w, a_b);
-              const float d0 = q2.z - R0[p], d1 = q2.w - R1[p], d2 = cb - R2[p];
-              const float dla = ti * fmaf(g0[p], d0, fmaf(g1[p], d1, g2[p] * d2));
-              R0[p] = fmaf(alpha, d0, R0[p]);
-              R1[p] = fmaf(alpha, d1, R1[p]);
-              R2[p] = fmaf(alpha, d2, R2[p]);
-              T[p] = ti;
-              if (oe <= kAlphaMax) {
-                a_o = fmaf(e, dla, a_o);
-                const float dq = dla * alpha;
-                const float du = dq * u;
-                a_u += du;
-                a_dy = fmaf(dq, dy, a_dy);
-                a_qa = fmaf(dq, u2, a_qa);
-                a_udy = fmaf(du, dy, a_udy);
-                a_qc = fmaf(dq, dy2, a_qc);
-              }
-            }
-          }
+          if (!((mk[p][c] >> jb) & 1u)) continue;  // uniform
+          const bool in = pos < last[p];
+          if (__ballot(in) == 0) continue;  // uniform
+          const float dx = (fx[p] - box.x) - q1.x;
+          const float dy = (fy[p] - box.z) - q1.y;
+          const float u = fmaf(q1.w, dy, dx);
+          const float u2 = u * u, dy2 = dy * dy;
+          const float q = fmaf(q1.z, u2, q2.x * dy2);
+          const float e = __builtin_amdgcn_exp2f(q);
+          const float oe = q2.y * e;
+          const float alpha = fminf(kAlphaMax, oe);
+          const bool comp = in & (alpha >= kAlphaMin);
+          if (__ballot(comp) == 0) continue;  // uniform
+          any = true;
+          const float am = comp ? alpha : 0.0f;
+          const float ti = T[p] * __builtin_amdgcn_rcpf(1.0f - am);
+          const float w = am * ti;
+          a_r = fmaf(g0[p], w, a_r);
+          a_g = fmaf(g1[p], w, a_g);
+          a_b = fmaf(g2[p], w, a_b);
+          const float d0 = q2.z - R0[p], d1 = q2.w - R1[p], d2 = cb - R2[p];
+          const float dla = ti * fmaf(g0[p], d0, fmaf(g1[p], d1, g2[p] * d2));
+          R0[p] = fmaf(am, d0, R0[p]);
+          R1[p] = fmaf(am, d1, R1[p]);
+          R2[p] = fmaf(am, d2, R2[p]);
+          T[p] = ti;
+          // below the 0.99 cap alpha = opacity 2^q; at the cap its
+          // derivative in opacity and q is zero
+          const bool uncapped = comp & (oe <= kAlphaMax);
+          const float eg = uncapped ? e : 0.0f;
+          const float dq = uncapped ? dla * alpha : 0.0f;
+          a_o = fmaf(eg, dla, a_o);
+          const float du = dq * u;
+          a_u += du;
+          a_dy = fmaf(dq, dy, a_dy);
+          a_qa = fmaf(dq, u2, a_qa);
+          a_udy = fmaf(du, dy, a_udy);
+          a_qc = fmaf(dq, dy2, a_qc);
         }
-      }
-      if (__ballot(any)) {
-        const float v9[9] = {a_u, a_dy, a_qa, a_udy, a_qc, a_o, a_r, a_g, a_b};
-        const float sum = wave_sum9_packed(v9);  // value l in lane l < 8, value 8 in lane 32
-        if (lane < 8 || lane == 32) L.g[((size_t)jj * NW + wv) * 9 + (lane < 8 ? lane : 8)] = sum;
+        if (any) {
+          const float v9[9] = {a_u, a_dy, a_qa, a_udy, a_qc, a_o, a_r, a_g, a_b};
+          const float sum = wave_sum9_packed(v9);  // value l in lane l < 8, value 8 in lane 32
+          if (lane < 8 || lane == 32) L.g[((size_t)jj * NW + wv) * 9 + (lane < 8 ? lane : 8)] = sum;
+        }
       }
     }
     group_sync<WG>();

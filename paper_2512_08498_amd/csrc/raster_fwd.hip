@@ -4,6 +4,10 @@
 //
 // Records are staged in LDS in batches (one per thread, four float4 each,
 // stored as four arrays so all lanes read the same address: LDS broadcast).
+// Each wave then walks only the records whose box meets one of its 8 x 8
+// pixel blocks (bit masks in scalar registers), and there every pixel not
+// yet stopped evaluates alpha: outside the box alpha < 1/255, so the
+// per-pixel alpha test alone decides which entries composite.
 // Per pixel the kernel keeps T, the colour and the position one past the
 // last composited entry, which the backward pass starts from.  With a
 // target image the L1 loss is fused into the epilogue: dL/dimage per pixel
@@ -59,8 +63,9 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
 
   int px[PPT], py[PPT];
   float fx[PPT], fy[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
-  uint32_t last[PPT], cnt[PPT];
-  bool done[PPT];
+  // live[p]: 1 while pixel p composites (a 32-bit word rather than a bool,
+  // so testing it is one compare instead of lane-mask bookkeeping)
+  uint32_t last[PPT], cnt[PPT], live[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     int x, y;
@@ -69,7 +74,7 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
     py[p] = ty * TS + y;
     fx[p] = (float)px[p];
     fy[p] = (float)py[p];
-    done[p] = !(px[p] < vi.w && py[p] < vi.h);
+    live[p] = (px[p] < vi.w && py[p] < vi.h) ? 1u : 0u;
     T[p] = 1.0f;
     C0[p] = C1[p] = C2[p] = 0.0f;
     last[p] = 0;
@@ -77,10 +82,10 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
   }
 
   for (uint32_t b0 = 0; b0 < n; b0 += B) {
-    bool alive = false;
+    uint32_t alive = 0;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) alive |= !done[p];
-    if (!group_any<WG>(alive)) break;
+    for (int p = 0; p < PPT; ++p) alive |= live[p];
+    if (!group_any<WG>(alive != 0u)) break;
     const uint32_t m = min((uint32_t)B, n - b0);
     if ((uint32_t)t < m) {
       uint32_t rec = ws.tile_recs[start + b0 + t];
@@ -95,34 +100,49 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
       L.p3[t] = src[3];
     }
     fwd_sync<WG>();
-    for (uint32_t j = 0; j < m; ++j) {
-      const float4 box = L.p0[j];
+    // records by 8 x 8 pixel block (wave-uniform bit masks): a wave visits
+    // only the records that can composite in one of its blocks
+    constexpr int NC = (B + kWave - 1) / kWave;
+    uint64_t mk[PPT][NC];
+    block_masks<PPT, NC>(L.p0, m, t, (float)(tx * TS), (float)(ty * TS), pix, mk);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        // bitwise, so the whole box is tested at once with a single branch
-        const bool in = !done[p] & (fx[p] >= box.x) & (fx[p] <= box.y) & (fy[p] >= box.z) & (fy[p] <= box.w);
-        if (in) {
-          const float4 q1 = L.p1[j], q2 = L.p2[j];
+    for (int c = 0; c < NC; ++c) {
+      uint64_t any = 0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) any |= mk[p][c];
+      while (any) {
+        const uint32_t jj = (uint32_t)__builtin_ctzll(any);
+        any &= any - 1;
+        const uint32_t j = (uint32_t)c * kWave + jj;
+        const float4 box = L.p0[j], q1 = L.p1[j], q2 = L.p2[j];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          // per 8 x 8 block: skipped (wave-uniform) unless one of its
+          // pixels is still compositing and reaches alpha >= 1/255; then
+          // branch-free, lanes that do not composite leaving their state
+          // as it is
+          if (!((mk[p][c] >> jj) & 1u)) continue;
+          if (__ballot(live[p] != 0u) == 0) continue;
           const float dx = (fx[p] - box.x) - q1.x;
           const float dy = (fy[p] - box.z) - q1.y;
           const float u = fmaf(q1.w, dy, dx);
           const float q = fmaf(q1.z, u * u, q2.x * (dy * dy));
           const float alpha = fminf(kAlphaMax, q2.y * __builtin_amdgcn_exp2f(q));
-          if (alpha >= kAlphaMin) {
-            const float tn = T[p] * (1.0f - alpha);
-            if (tn < kTMin) {
-              done[p] = true;
-            } else {
-              const float w = alpha * T[p];
-              const float b = L.p3[j].x;
-              C0[p] = fmaf(w, q2.z, C0[p]);
-              C1[p] = fmaf(w, q2.w, C1[p]);
-              C2[p] = fmaf(w, b, C2[p]);
-              T[p] = tn;
-              last[p] = b0 + j + 1;
-              cnt[p] += 1;
-            }
-          }
+          const bool hit = (live[p] != 0u) & (alpha >= kAlphaMin);
+          if (__ballot(hit) == 0) continue;
+          // stop before the entry that would take T below 1e-4
+          const float tn = T[p] * (1.0f - alpha);
+          const bool stop = hit & (tn < kTMin);
+          const bool comp = hit & !stop;
+          live[p] = stop ? 0u : live[p];
+          const float w = comp ? alpha * T[p] : 0.0f;
+          const float b = L.p3[j].x;
+          C0[p] = fmaf(w, q2.z, C0[p]);
+          C1[p] = fmaf(w, q2.w, C1[p]);
+          C2[p] = fmaf(w, b, C2[p]);
+          T[p] = comp ? tn : T[p];
+          last[p] = comp ? b0 + j + 1 : last[p];
+          cnt[p] += comp ? 1u : 0u;
         }
       }
     }
