@@ -96,7 +96,7 @@ def stage_work(stage, n, n_u, pg, views, px, rec, pairs, tiles, evals):
 
 
 STEP_STAGES = ("preprocess", "binning", "sort", "raster_fwd", "loss", "raster_bwd", "reduce", "pre_bwd")
-STAGE_KERNEL = {"raster_bwd": "k_raster_bwd16", "raster_fwd": "k_raster_fwd<16>", "preprocess": "k_pre_write<3>",
+STAGE_KERNEL = {"raster_bwd": "k_raster_bwd16", "raster_fwd": "k_raster_fwd16", "preprocess": "k_pre_write<3>",
                 "pre_bwd": "k_pre_bwd<3,true>"}
 
 
@@ -260,7 +260,7 @@ def batching_comparison(scene, cams, target, params, rast, dev, steps, warmup, r
     rs = []
     for c in cams:
         r = Rasterizer([c], scene.n, scene.sh_degree, tile_size=tun["tile_size"], long_list=tun["long_list"],
-                       device=dev, capacity_records=max(scene.n // 4, 65536), capacity_pairs=max(scene.n, 262144))
+                       persistent=tun["persistent"], device=dev, capacity_records=max(scene.n // 4, 65536), capacity_pairs=max(scene.n, 262144))
         r.forward(params)
         rr, pp, _ = r.required_capacity()
         r._plan(int(rr * 1.5) + 4096, int(pp * 1.5) + 65536)
@@ -351,6 +351,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--tile-size", type=int, default=0, help="8, 16 or 32; 0 (default) = autotune on the workload")
+    ap.add_argument("--persistent", type=int, default=0, choices=(0, 1),
+                    help="with --tile-size: 1 = persistent compositing launches (the autotuner chooses otherwise)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
@@ -403,7 +405,7 @@ def main():
 
     cap_rec = max(len(cams) * scene.n // 4, 65536)
     rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=args.tile_size or 16, device=dev,
-                      capacity_records=cap_rec, capacity_pairs=4 * cap_rec)
+                      capacity_records=cap_rec, capacity_pairs=4 * cap_rec, persistent=bool(args.persistent))
     out = rast.forward(params)  # re-plans on capacity overflow
     rec, pairs, tiles = rast.required_capacity()
     # headroom for the scene to move during training

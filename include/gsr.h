@@ -294,16 +294,24 @@ gsr_status gsr_profile_read(gsr_ctx *ctx, double *ms, int64_t *calls, int32_t re
  *             8 x 8 quadrant each, one pixel per lane); shorter tiles take one
  *             wave each (four pixels per lane), four tiles per workgroup.
  *             0 sends every tile to the four-wave walk, 0xFFFFFFFF none.
+ *  persistent 0: one workgroup per work item (a tile, or at 16 px a group
+ *             of four short tiles), dispatched by the hardware in the
+ *             longest-first order.  1: a persistent launch of as many
+ *             workgroups as the device holds at once, each taking work items
+ *             in that order from a queue of eight device counters (one per
+ *             XCD) until none is left.  Results are identical.
  *  step_ms    (gsr_autotune output) measured forward + backward time.     */
 typedef struct {
   int32_t tile_size;
   uint32_t long_list;
+  int32_t persistent;
   float step_ms;
 } gsr_tuning;
 
 /* Set the tuning (HOST struct) used by the next gsr_plan, or read the
- * current one.  Defaults: tile size 16, long_list 1024.
- * Errors: INVALID_ARG for a tile size other than 8/16/32.                  */
+ * current one.  Defaults: tile size 16, long_list 1024, persistent 0.
+ * Errors: INVALID_ARG for a tile size other than 8/16/32 or persistent
+ * other than 0/1.                                                          */
 gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
 gsr_status gsr_get_tuning(gsr_ctx *ctx, gsr_tuning *t);
 
@@ -475,8 +483,11 @@ gsr_status gsr_merge(gsr_ctx *ctx, const gsr_gaussians *g, int32_t view, const g
 /* Autotuner of the batched launch (the keyframe-window batches of Sec. 3.3
  * mix resolutions, so no one tile size suits all): times forward plus
  * backward on this batch for tile sizes 8, 16 and 32 and, at 16, for
- * long_list in {0, 256, 512, 1024, 0xFFFFFFFF}, and keeps the fastest
- * (median of `repeats` >= 1 timed passes after one warm-up pass).
+ * long_list in {0, 256, 512, 1024, 0xFFFFFFFF}, each with the grid and the
+ * persistent schedule (gsr_tuning), and keeps the fastest (median of
+ * `repeats` >= 1 timed passes after one warm-up pass); candidates are tried
+ * grid schedule first, 16 px with long_list 1024 first, and a later one is
+ * kept only if at least 1% faster than the choice so far.
  * g: the Gaussians (DEVICE arrays); cams_host: HOST cameras; opt: capacities
  * and background as for gsr_plan (tile_size ignored; NULL = defaults).  With
  * cache_path (NULL = none) the choice is looked up first in that text file,

@@ -41,7 +41,8 @@ class PlanOptions(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("tile_size", C.c_int32), ("long_list", C.c_uint32), ("step_ms", C.c_float)]
+    _fields_ = [("tile_size", C.c_int32), ("long_list", C.c_uint32), ("persistent", C.c_int32),
+                ("step_ms", C.c_float)]
 
 
 class FwdOut(C.Structure):

@@ -1,6 +1,7 @@
 // Autotuner of the batched launch: measures forward + backward on the
-// caller's batch for each candidate launch configuration (tile size, and at
-// 16 px the backward's long-list split) and keeps the fastest.  Built on the
+// caller's batch for each candidate launch configuration (tile size, at
+// 16 px the long-list split, and the grid or persistent schedule) and keeps
+// the fastest.  Built on the
 // public entry points; its device buffers live only for the measurement.
 #include <hip/hip_runtime.h>
 
@@ -81,9 +82,9 @@ bool cache_lookup(const char *path, const std::string &key, gsr_tuning *t, bool 
     const size_t sp = line.find(' ');
     if (sp != std::string::npos && line.compare(0, sp, key) == 0 && sp == key.size()) {
       gsr_tuning u{};
-      if (sscanf(line.c_str() + sp, " tile_size=%d long_list=%u step_ms=%f", &u.tile_size, &u.long_list,
-                 &u.step_ms) == 3 &&
-          (u.tile_size == 8 || u.tile_size == 16 || u.tile_size == 32)) {
+      if (sscanf(line.c_str() + sp, " tile_size=%d long_list=%u persistent=%d step_ms=%f", &u.tile_size,
+                 &u.long_list, &u.persistent, &u.step_ms) == 4 &&
+          (u.tile_size == 8 || u.tile_size == 16 || u.tile_size == 32) && (u.persistent == 0 || u.persistent == 1)) {
         *t = u;
         found = true;
         *malformed = false;
@@ -124,8 +125,12 @@ extern "C" gsr_status gsr_autotune(gsr_ctx *c, const gsr_gaussians *g, const gsr
     if (malformed) return ctx_error(c, GSR_ERR_INVALID_ARG, "malformed autotune cache line for this batch");
   }
 
-  const gsr_tuning candidates[] = {{16, 512u, 0.f},  {16, 256u, 0.f}, {16, 1024u, 0.f}, {16, 0u, 0.f},
-                                   {16, 0xFFFFFFFFu, 0.f}, {8, 512u, 0.f}, {32, 512u, 0.f}};
+  std::vector<gsr_tuning> candidates;
+  for (int pers = 0; pers < 2; ++pers) {
+    for (uint32_t ll : {1024u, 512u, 256u, 0u, 0xFFFFFFFFu}) candidates.push_back({16, ll, pers, 0.f});
+    candidates.push_back({8, 512u, pers, 0.f});
+    candidates.push_back({32, 512u, pers, 0.f});
+  }
   gsr_tuning keep{};
   gsr_status st = gsr_get_tuning(c, &keep);
   if (st != GSR_OK) return st;
@@ -225,8 +230,11 @@ extern "C" gsr_status gsr_autotune(gsr_ctx *c, const gsr_gaussians *g, const gsr
     if (st != GSR_OK) break;
     if ((st = gsr_check(c, ws.p, s)) != GSR_OK) break;
     std::sort(times.begin(), times.end());
+    // candidates are listed in order of preference (the grid schedule
+    // first); a later one must be at least 1% faster to replace the choice,
+    // so timing noise between near-equal configurations does not decide
     const float med = times[repeats / 2];
-    if (best_ms == 0.0f || med < best_ms) {
+    if (best_ms == 0.0f || med < 0.99f * best_ms) {
       best_ms = med;
       chosen = cand;
       chosen.step_ms = med;
@@ -245,8 +253,8 @@ extern "C" gsr_status gsr_autotune(gsr_ctx *c, const gsr_gaussians *g, const gsr
   if (cache_path) {
     FILE *f = fopen(cache_path, "a");
     if (!f) return ctx_error(c, GSR_ERR_INVALID_ARG, "gsr_autotune: cannot append to the cache file");
-    fprintf(f, "%s tile_size=%d long_list=%u step_ms=%.4f\n", key.c_str(), chosen.tile_size, chosen.long_list,
-            chosen.step_ms);
+    fprintf(f, "%s tile_size=%d long_list=%u persistent=%d step_ms=%.4f\n", key.c_str(), chosen.tile_size,
+            chosen.long_list, chosen.persistent, chosen.step_ms);
     fclose(f);
   }
   return GSR_OK;

@@ -37,6 +37,8 @@ enum Scalar : int {
 // Workspace arrays (device pointers into the caller's workspace).
 struct Ws {
   uint32_t *scalars;        // [kNumScalars]              zeroed per forward
+  uint32_t *queues;         // [2][kQueueLanes][kQueueStride] compositing work queues (forward, backward),
+                            //                            zeroed per forward
   uint32_t *tile_count;     // [T_tot] list length        zeroed per forward
   uint32_t *tile_start;     // [T_tot] list start         zeroed per forward
   uint2 *block_sums;        // [n_blocks] (records, pairs) -> exclusive offsets
@@ -70,11 +72,14 @@ struct Sizes {
   uint32_t cap_pairs;
   uint32_t n_blocks;        // ceil(n / kPreBlock)
   uint32_t long_list;       // 16 px tiles: lists this long are walked by four waves in the backward
+  uint32_t persistent;      // compositing: 1 = persistent workgroups over a work queue (ItemQueue)
   uint32_t vis_words;       // ceil(n_views / 64)
   float bg[3];
 };
 
 constexpr int kPreBlock = 256;     // Gaussians per preprocess workgroup
+constexpr int kQueueLanes = 8;     // counters per work queue: one per XCD
+constexpr int kQueueStride = 32;   // words between counters (one 128-byte line each)
 constexpr int kLossBlocks = 2048;  // loss reduction partials
 
 // Image-model constants (float32 bit patterns written as hex literals).

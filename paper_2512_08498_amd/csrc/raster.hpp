@@ -1,6 +1,7 @@
 // Tile geometry shared by the forward and backward compositing kernels.
 //
-// A tile of TS x TS pixels is processed by one workgroup.  Records are staged
+// A tile of TS x TS pixels is walked by one workgroup, or at 16 px by one
+// wave of it, taken from a work queue by a persistent launch.  Records are staged
 // in LDS in batches and read back as broadcasts; a record whose pixel box
 // misses a lane's pixel costs only the box test (the per-lane test clears
 // the exec mask and the body is branched over).  The forward and the
@@ -183,6 +184,65 @@ __device__ __forceinline__ void pixel_of(int t, int p, int &x, int &y) {
     x += (w & 1) * 16;
     y += (w >> 1) * 16;
   }
+}
+
+// Persistent compositing launches: as many workgroups as the chip holds at
+// once, each walking work items (tiles, or groups of tiles, in the
+// longest-first order) until none is left; taking an item never waits for
+// another workgroup, so the balance adapts at run time to the actual cost of
+// each list.  Item i belongs to lane i % 8 of the queue, and workgroup b
+// serves lane b % 8: its first item is b itself, later ones come from that
+// lane's counter, one atomic add per item (lane-local index gridDim.x / 8 +
+// count).  The grid is a multiple of eight, so every lane has workgroups and
+// every item is taken exactly once, however the workgroups are placed.  The
+// chip dispatches workgroups to its eight XCDs round-robin, so each counter
+// (on a 128-byte line of its own) is used from one XCD: the eight are served
+// in parallel, where a single counter for all workgroups serialised the
+// atomics and doubled the compositing time.  The add for the next item is
+// issued when the current one starts, so its latency is hidden behind the
+// walk.  A workgroup stops at its first item past the end; the claim it
+// still has in flight then lies past the end too (a lane's items grow with
+// its count), so no item is lost.  The counters start at zero: the
+// forward's first kernel zeroes both queues, and the pair reduction that
+// follows every compositing backward zeroes the backward's again.
+// Without persistence (P = false) the grid has one workgroup per item and
+// next() ends the walk after the first; the kernels are instantiated for
+// both, so the grid schedule carries no queue state.
+template <bool P>
+struct ItemQueue {
+  uint32_t *ctr;   // the lane's counter
+  uint32_t claim;  // thread 0: lane-local count claimed for the next item
+
+  __device__ __forceinline__ explicit ItemQueue(uint32_t *queue)
+      : ctr(queue + (blockIdx.x & (kQueueLanes - 1u)) * kQueueStride), claim(0u) {
+    if (P && threadIdx.x == 0) claim = atomicAdd(ctr, 1u);
+  }
+
+  // Next item of the calling workgroup (uniform); every thread must call it,
+  // after its last access to the LDS of the current item.
+  __device__ __forceinline__ uint32_t next(uint32_t *slot) {
+    if (!P) return 0xFFFFFFFFu;
+    if (threadIdx.x == 0) *slot = claim;
+    __syncthreads();
+    const uint32_t k = *slot;
+    __syncthreads();
+    if (threadIdx.x == 0) claim = atomicAdd(ctr, 1u);
+    return (gridDim.x / kQueueLanes + k) * kQueueLanes + (blockIdx.x & (kQueueLanes - 1u));
+  }
+};
+
+// Workgroups of a persistent launch: compute units times the workgroups of
+// `kernel` (of `threads` threads) that one holds at once, a multiple of the
+// queue's lanes.
+template <typename K>
+inline uint32_t persistent_grid(K kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+  const uint32_t g = (uint32_t)(cus * per) / kQueueLanes * kQueueLanes;
+  return g < (uint32_t)kQueueLanes ? (uint32_t)kQueueLanes : g;
 }
 
 }  // namespace gsr

@@ -288,14 +288,14 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
   }
 }
 
-// 16 px tiles.  Tiles whose list has at least Sizes::long_list entries (a
-// prefix of the longest-first order, autotuned) take a whole workgroup: four waves, each an
-// 8 x 8 quadrant with one pixel per lane, sharing 128-record LDS batches,
-// so a long list is walked four times faster.  The remaining tiles are
-// packed four to a workgroup, one wave each (16 x 16 pixels, four per lane),
-// so each record's wave reduction is paid once per tile; neighbours in the
-// longest-first order have similar lengths, so the four waves finish
-// together.
+// 16 px tiles, persistent (see ItemQueue).  Tiles whose list has at least
+// Sizes::long_list entries (a prefix of the longest-first order, autotuned)
+// are one work item each, for the whole workgroup: four waves, each an
+// 8 x 8 quadrant with one pixel per lane, sharing 128-record LDS batches, so
+// a long list is walked four times faster.  The remaining tiles are items of
+// four, one wave each (16 x 16 pixels, four per lane), so each record's wave
+// reduction is paid once per tile; neighbours in the longest-first order
+// have similar lengths, so the four waves finish together.
 
 union BwdLds16 {
   BwdLds<128, 4> quad;
@@ -305,50 +305,55 @@ union BwdLds16 {
 // Five waves per SIMD: 96 VGPRs instead of 110 (four waves), with 14 values
 // kept in scratch, and measured 8% faster than four waves without spills.
 // Six would need more than the CU's 160 KB of LDS.
+template <bool P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raster_bwd16(
-    const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
-                                                      const float *__restrict__ t_final,
-                                                      const uint32_t *__restrict__ last_pos,
-                                                      const float *__restrict__ dL_dimage) {
+    const ViewInfo *__restrict__ views, Ws ws, Sizes sz, const float *__restrict__ t_final,
+    const uint32_t *__restrict__ last_pos, const float *__restrict__ dL_dimage) {
   __shared__ BwdLds16 S;
+  __shared__ uint32_t take;
   if (ws.scalars[kOverflow]) return;
+  uint32_t *queue = ws.queues + kQueueLanes * kQueueStride;
   const uint32_t n_long = ws.scalars[kNumLong];
+  const uint32_t n_items = n_long + (sz.t_tot - n_long + 3u) / 4u;
   const int t = threadIdx.x;
-  if (blockIdx.x < n_long) {
-    const uint32_t tile = ws.tile_order[blockIdx.x];
-    bwd_walk<16, 256, 1, true, 128>(views, ws, sz, tile, t, S.quad, t_final, last_pos, dL_dimage,
-                                    [](int tt, int, int &x, int &y) {
-                                      const int l = tt & 63, w = tt >> 6;
-                                      x = (w & 1) * 8 + (l & 7);
-                                      y = (w >> 1) * 8 + (l >> 3);
-                                    });
-  } else {
-    const uint32_t i = n_long + (blockIdx.x - n_long) * 4u + (uint32_t)wave_id();
-    if (i >= sz.t_tot) return;
-    const uint32_t tile = ws.tile_order[i];
-    bwd_walk<16, 64, 4, false, 64>(views, ws, sz, tile, lane_id(), S.wave[wave_id()], t_final, last_pos,
-                                   dL_dimage, [](int tt, int p, int &x, int &y) {
-                                     x = (tt & 7) + (p & 1) * 8;
-                                     y = (tt >> 3) + (p >> 1) * 8;
-                                   });
+  ItemQueue<P> q(queue);
+  for (uint32_t it = blockIdx.x; it < n_items; it = q.next(&take)) {
+    if (it < n_long) {
+      bwd_walk<16, 256, 1, true, 128>(views, ws, sz, ws.tile_order[it], t, S.quad, t_final, last_pos, dL_dimage,
+                                      [](int tt, int, int &x, int &y) {
+                                        const int l = tt & 63, w = tt >> 6;
+                                        x = (w & 1) * 8 + (l & 7);
+                                        y = (w >> 1) * 8 + (l >> 3);
+                                      });
+    } else {
+      const uint32_t i = n_long + (it - n_long) * 4u + (uint32_t)wave_id();
+      if (i < sz.t_tot)
+        bwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], t_final,
+                                       last_pos, dL_dimage, [](int tt, int p, int &x, int &y) {
+                                         x = (tt & 7) + (p & 1) * 8;
+                                         y = (tt >> 3) + (p >> 1) * 8;
+                                       });
+    }
   }
 }
 
-// 8 and 32 px tiles: one workgroup per tile (one wave at 8 px with one pixel
-// per lane; four waves at 32 px, one 16 x 16 quadrant each).
-template <int TS>
-__global__ __launch_bounds__(TileCfg<TS>::NT) void k_raster_bwd(const ViewInfo *__restrict__ views, Ws ws,
+// 8 and 32 px tiles, persistent: one tile per work item, longest lists
+// first (one wave at 8 px with one pixel per lane; four waves
+// at 32 px, one 16 x 16 quadrant each).
+template <int TS, bool P>
+__global__ __launch_bounds__(TileCfg<TS>::NT) __attribute__((amdgpu_waves_per_eu(TS == 32 ? 4 : 6))) void k_raster_bwd(const ViewInfo *__restrict__ views, Ws ws,
                                                                 Sizes sz, const float *__restrict__ t_final,
                                                                 const uint32_t *__restrict__ last_pos,
                                                                 const float *__restrict__ dL_dimage) {
   constexpr int NT = TileCfg<TS>::NT, PPT = TileCfg<TS>::PPT;
   constexpr int B = NT >= 128 ? 128 : NT;
   __shared__ BwdLds<B, NT / kWave> S;
+  __shared__ uint32_t take;
   if (ws.scalars[kOverflow]) return;
-  if (blockIdx.x >= sz.t_tot) return;
-  const uint32_t tile = ws.tile_order[blockIdx.x];  // longest lists first
-  bwd_walk<TS, NT, PPT, true, B>(views, ws, sz, tile, threadIdx.x, S, t_final, last_pos, dL_dimage,
-                                 [](int tt, int p, int &x, int &y) { pixel_of<TS>(tt, p, x, y); });
+  ItemQueue<P> q(ws.queues + kQueueLanes * kQueueStride);
+  for (uint32_t i = blockIdx.x; i < sz.t_tot; i = q.next(&take))
+    bwd_walk<TS, NT, PPT, true, B>(views, ws, sz, ws.tile_order[i], threadIdx.x, S, t_final, last_pos, dL_dimage,
+                                   [](int tt, int p, int &x, int &y) { pixel_of<TS>(tt, p, x, y); });
 }
 
 // Sum each record's per-tile partials (contiguous, record-major) into its
@@ -371,6 +376,9 @@ __device__ __forceinline__ void add_partial(const float4 *__restrict__ src, floa
 // a capacity overflow nothing is updated (the per-Gaussian kernel skips its
 // Adam step too), so the counter stays with the moments.
 __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
+  // the next backward's work queue starts from zero
+  if (blockIdx.x == 0 && threadIdx.x < kQueueLanes)
+    ws.queues[(kQueueLanes + threadIdx.x) * kQueueStride] = 0u;
   if (ws.scalars[kOverflow]) return;
   if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
   const uint32_t nrec = ws.scalars[kNumRecords];
@@ -421,21 +429,30 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
   }
 }
 
+// Grid or persistent schedule, as the forward (launch_items there).
+template <bool P, class K, class... A>
+static void launch_items(K kernel, uint32_t t_tot, int threads, hipStream_t st, A... args) {
+  uint32_t grid = t_tot;
+  if (P) {
+    static const uint32_t pgrid = persistent_grid(kernel, threads);
+    grid = pgrid;
+  }
+  kernel<<<grid, threads, 0, st>>>(args...);
+}
+
 void launch_raster_bwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, const float *t_final,
                        const uint32_t *last_pos, const float *dL_dimage, hipStream_t st) {
   if (sz.t_tot == 0) return;
-  switch (sz.ts) {
-    case 8:
-      k_raster_bwd<8><<<sz.t_tot, TileCfg<8>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-      break;
-    case 32:
-      k_raster_bwd<32><<<sz.t_tot, TileCfg<32>::NT, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-      break;
-    default:
-      // at most t_tot workgroups: one per long tile, then one per four tiles
-      k_raster_bwd16<<<sz.t_tot, 256, 0, st>>>(views, ws, sz, t_final, last_pos, dL_dimage);
-      break;
+#define BWD_ARGS views, ws, sz, t_final, last_pos, dL_dimage
+  switch ((sz.ts << 1) | (sz.persistent ? 1 : 0)) {
+    case 16: launch_items<false>(k_raster_bwd<8, false>, sz.t_tot, TileCfg<8>::NT, st, BWD_ARGS); break;
+    case 17: launch_items<true>(k_raster_bwd<8, true>, sz.t_tot, TileCfg<8>::NT, st, BWD_ARGS); break;
+    case 64: launch_items<false>(k_raster_bwd<32, false>, sz.t_tot, TileCfg<32>::NT, st, BWD_ARGS); break;
+    case 65: launch_items<true>(k_raster_bwd<32, true>, sz.t_tot, TileCfg<32>::NT, st, BWD_ARGS); break;
+    case 33: launch_items<true>(k_raster_bwd16<true>, sz.t_tot, 256, st, BWD_ARGS); break;
+    default: launch_items<false>(k_raster_bwd16<false>, sz.t_tot, 256, st, BWD_ARGS); break;
   }
+#undef BWD_ARGS
 }
 
 void launch_reduce_pairs(const Ws &ws, const Sizes &sz, int32_t *step, hipStream_t st) {

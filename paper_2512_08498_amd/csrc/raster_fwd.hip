@@ -11,9 +11,10 @@
 // Per pixel the kernel keeps T, the colour and the position one past the
 // last composited entry, which the backward pass starts from.  With a
 // target image the L1 loss is fused into the epilogue: dL/dimage per pixel
-// and |image - target| summed per workgroup (a fixed butterfly per wave, then
-// the waves in order), one partial per workgroup, added up in order by
-// k_l1_sum.
+// and |image - target| summed per tile (a fixed butterfly per wave, then the
+// waves in order), one partial per tile, added up in tile order by k_l1_sum.
+// Both compositing passes are persistent launches that take tiles from a
+// work queue (ItemQueue in raster.hpp).
 #include "kernels.hpp"
 #include "raster.hpp"
 #include "util.hpp"
@@ -175,11 +176,12 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
   }
 }
 
-// Sum of the loss accumulators of a workgroup of NW waves into its partial
-// slot: a butterfly per wave, then the waves in order (every thread of the
-// workgroup must take part).
+// The fused loss keeps one partial per tile (its item in the longest-first
+// order), so its fixed-order sum does not depend on which workgroup took
+// which tile.  A workgroup's tile: a butterfly per wave, then the waves in
+// order (every thread takes part); a wave's tile: its butterfly alone.
 template <int NW>
-__device__ __forceinline__ void loss_partial(const LossArgs &la, float acc, float *red) {
+__device__ __forceinline__ void tile_loss_group(const LossArgs &la, float acc, float *red, uint32_t item) {
   if (!la.target) return;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
@@ -189,87 +191,119 @@ __device__ __forceinline__ void loss_partial(const LossArgs &la, float acc, floa
     float s = red[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) s += red[w];
-    la.part[blockIdx.x] = s;
+    la.part[item] = s;
   }
+  __syncthreads();
 }
 
-// 16 px tiles: lists of at least long_list entries (a prefix of the
-// longest-first order) are shared by four waves, one 8 x 8 quadrant each
-// with one pixel per lane; the other tiles take one wave each (16 x 16
-// pixels, four per lane), four tiles per workgroup, so each record is tested
-// once per tile rather than once per quadrant.
+__device__ __forceinline__ void tile_loss_wave(const LossArgs &la, float acc, uint32_t item) {
+  if (!la.target) return;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (lane_id() == 0) la.part[item] = acc;
+}
+
+// 16 px tiles, persistent: lists of at least long_list entries (a prefix
+// of the longest-first order) are one work item each, shared by the four
+// waves of the workgroup, one 8 x 8 quadrant each with one pixel per lane;
+// the other tiles are items of four, one per wave (16 x 16 pixels, four per
+// lane), so each record is tested once per tile rather than once per
+// quadrant, and neighbours in the longest-first order (of similar length)
+// finish together.
 union FwdLds16 {
   FwdLds<256> quad;
   FwdLds<64> wave[4];
 };
 
-__global__ __launch_bounds__(256) void k_raster_fwd16(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
-                                                      float *__restrict__ image, float *__restrict__ t_final,
-                                                      uint32_t *__restrict__ last_pos,
-                                                      uint32_t *__restrict__ n_contrib, LossArgs la) {
+template <bool P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_fwd16(
+    const ViewInfo *__restrict__ views, Ws ws, Sizes sz, float *__restrict__ image, float *__restrict__ t_final,
+    uint32_t *__restrict__ last_pos, uint32_t *__restrict__ n_contrib, LossArgs la) {
   __shared__ FwdLds16 S;
   __shared__ float red[4];
+  __shared__ uint32_t take;
   if (ws.scalars[kOverflow]) return;
+  uint32_t *queue = ws.queues;
+  // items: the n_long long tiles one by one, then the others four at a time
   const uint32_t n_long = ws.scalars[kNumLong];
+  const uint32_t n_items = n_long + (sz.t_tot - n_long + 3u) / 4u;
   const int t = threadIdx.x;
-  float acc = 0.0f;
-  if (blockIdx.x < n_long) {
-    fwd_walk<16, 256, 1, true, 256>(views, ws, sz, ws.tile_order[blockIdx.x], t, S.quad, image, t_final, last_pos,
-                                    n_contrib, la, acc, [](int tt, int, int &x, int &y) {
-                                      const int l = tt & 63, w = tt >> 6;
-                                      x = (w & 1) * 8 + (l & 7);
-                                      y = (w >> 1) * 8 + (l >> 3);
-                                    });
-  } else {
-    const uint32_t i = n_long + (blockIdx.x - n_long) * 4u + (uint32_t)wave_id();
-    if (i < sz.t_tot)
-      fwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], image, t_final,
-                                     last_pos, n_contrib, la, acc, [](int tt, int p, int &x, int &y) {
-                                       x = (tt & 7) + (p & 1) * 8;
-                                       y = (tt >> 3) + (p >> 1) * 8;
-                                     });
+  ItemQueue<P> q(queue);
+  for (uint32_t it = blockIdx.x; it < n_items; it = q.next(&take)) {
+    if (it < n_long) {
+      float acc = 0.0f;
+      fwd_walk<16, 256, 1, true, 256>(views, ws, sz, ws.tile_order[it], t, S.quad, image, t_final, last_pos,
+                                      n_contrib, la, acc, [](int tt, int, int &x, int &y) {
+                                        const int l = tt & 63, w = tt >> 6;
+                                        x = (w & 1) * 8 + (l & 7);
+                                        y = (w >> 1) * 8 + (l >> 3);
+                                      });
+      tile_loss_group<4>(la, acc, red, it);
+    } else {
+      const uint32_t i = n_long + (it - n_long) * 4u + (uint32_t)wave_id();
+      if (i < sz.t_tot) {
+        float acc = 0.0f;
+        fwd_walk<16, 64, 4, false, 64>(views, ws, sz, ws.tile_order[i], lane_id(), S.wave[wave_id()], image,
+                                       t_final, last_pos, n_contrib, la, acc, [](int tt, int p, int &x, int &y) {
+                                         x = (tt & 7) + (p & 1) * 8;
+                                         y = (tt >> 3) + (p >> 1) * 8;
+                                       });
+        tile_loss_wave(la, acc, i);
+      }
+    }
   }
-  loss_partial<4>(la, acc, red);
 }
 
-// 8 and 32 px tiles: one workgroup per tile (FwdTile), longest lists first.
-template <int TS>
-__global__ __launch_bounds__(FwdTile<TS>::NT) void k_raster_fwd(const ViewInfo *__restrict__ views, Ws ws,
-                                                                Sizes sz, float *__restrict__ image,
-                                                                float *__restrict__ t_final,
-                                                                uint32_t *__restrict__ last_pos,
-                                                                uint32_t *__restrict__ n_contrib, LossArgs la) {
+// 8 and 32 px tiles, persistent: a workgroup (FwdTile) takes one tile at a
+// time, longest lists first.
+template <int TS, bool P>
+__global__ __launch_bounds__(FwdTile<TS>::NT) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 8 : 6))) void k_raster_fwd(
+    const ViewInfo *__restrict__ views, Ws ws, Sizes sz, float *__restrict__ image, float *__restrict__ t_final,
+    uint32_t *__restrict__ last_pos, uint32_t *__restrict__ n_contrib, LossArgs la) {
   constexpr int NT = FwdTile<TS>::NT, PPT = FwdTile<TS>::PPT;
   __shared__ FwdLds<NT> S;
   __shared__ float red[NT / 64];
+  __shared__ uint32_t take;
   if (ws.scalars[kOverflow]) return;
-  float acc = 0.0f;
-  if (blockIdx.x < sz.t_tot)
-    fwd_walk<TS, NT, PPT, true, NT>(views, ws, sz, ws.tile_order[blockIdx.x], threadIdx.x, S, image, t_final,
-                                    last_pos, n_contrib, la, acc,
+  ItemQueue<P> q(ws.queues);
+  for (uint32_t i = blockIdx.x; i < sz.t_tot; i = q.next(&take)) {
+    float acc = 0.0f;
+    fwd_walk<TS, NT, PPT, true, NT>(views, ws, sz, ws.tile_order[i], threadIdx.x, S, image, t_final, last_pos,
+                                    n_contrib, la, acc,
                                     [](int tt, int p, int &x, int &y) { fwd_pixel<TS>(tt, p, x, y); });
-  loss_partial<NT / 64>(la, acc, red);
+    tile_loss_group<NT / 64>(la, acc, red, i);
+  }
 }
 
-// Workgroups of the forward launch (the fused loss has one partial per workgroup).
-uint32_t raster_fwd_grid(const Sizes &sz) { return sz.ts == 16 ? sz.t_tot : tile_grid(sz.t_tot); }
+// Loss partials of the forward: one per tile.
+uint32_t raster_fwd_grid(const Sizes &sz) { return sz.t_tot; }
+
+// Grid schedule: one workgroup per item, at most t_tot (at 16 px one per
+// long tile, then one per four tiles; the count of long tiles is known on
+// the device only).  Persistent: the device's resident workgroups.
+template <bool P, class K, class... A>
+static void launch_items(K kernel, uint32_t t_tot, int threads, hipStream_t st, A... args) {
+  uint32_t grid = t_tot;
+  if (P) {
+    static const uint32_t pgrid = persistent_grid(kernel, threads);
+    grid = pgrid;
+  }
+  kernel<<<grid, threads, 0, st>>>(args...);
+}
 
 void launch_raster_fwd(const ViewInfo *views, const Ws &ws, const Sizes &sz, float *image, float *t_final,
                        uint32_t *last_pos, uint32_t *n_contrib, const LossArgs &la, hipStream_t st) {
-  const uint32_t grid = raster_fwd_grid(sz);
-  if (grid == 0) return;
-  switch (sz.ts) {
-    case 8:
-      k_raster_fwd<8><<<grid, FwdTile<8>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
-      break;
-    case 32:
-      k_raster_fwd<32><<<grid, FwdTile<32>::NT, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
-      break;
-    default:
-      // at most t_tot workgroups: one per long tile, then one per four tiles
-      k_raster_fwd16<<<grid, 256, 0, st>>>(views, ws, sz, image, t_final, last_pos, n_contrib, la);
-      break;
+  if (sz.t_tot == 0) return;
+#define FWD_ARGS views, ws, sz, image, t_final, last_pos, n_contrib, la
+  switch ((sz.ts << 1) | (sz.persistent ? 1 : 0)) {
+    case 16: launch_items<false>(k_raster_fwd<8, false>, sz.t_tot, FwdTile<8>::NT, st, FWD_ARGS); break;
+    case 17: launch_items<true>(k_raster_fwd<8, true>, sz.t_tot, FwdTile<8>::NT, st, FWD_ARGS); break;
+    case 64: launch_items<false>(k_raster_fwd<32, false>, sz.t_tot, FwdTile<32>::NT, st, FWD_ARGS); break;
+    case 65: launch_items<true>(k_raster_fwd<32, true>, sz.t_tot, FwdTile<32>::NT, st, FWD_ARGS); break;
+    case 33: launch_items<true>(k_raster_fwd16<true>, sz.t_tot, 256, st, FWD_ARGS); break;
+    default: launch_items<false>(k_raster_fwd16<false>, sz.t_tot, 256, st, FWD_ARGS); break;
   }
+#undef FWD_ARGS
 }
 
 }  // namespace gsr

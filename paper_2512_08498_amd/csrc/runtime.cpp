@@ -19,7 +19,7 @@ using namespace gsr;
 namespace {
 
 struct Layout {
-  size_t scalars, tile_count, tile_start, zero_end;
+  size_t scalars, queues, tile_count, tile_start, zero_end;
   size_t block_sums, vis_mask, rec_start, payload, rec_g, rec_view, rec_pairoff, rec_rect, rec_zbits;
   size_t rec_tmp, tile_order, tile_tmp, radix_hist, scan_part, pairs_tmp, tile_recs, partials, g2d, cam_part, loss_part;
   size_t total;
@@ -57,6 +57,7 @@ struct gsr_ctx {
   // tuning applied at the next gsr_plan
   int32_t tuned_ts = 16;
   uint32_t long_list = 1024;
+  int32_t persistent = 0;
   // stage timing
   bool prof = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -108,6 +109,7 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   const Layout &L = c->lay;
   Ws w;
   w.scalars = reinterpret_cast<uint32_t *>(b + L.scalars);
+  w.queues = reinterpret_cast<uint32_t *>(b + L.queues);
   w.block_sums = reinterpret_cast<uint2 *>(b + L.block_sums);
   w.vis_mask = reinterpret_cast<uint64_t *>(b + L.vis_mask);
   w.rec_start = reinterpret_cast<uint32_t *>(b + L.rec_start);
@@ -145,6 +147,7 @@ Layout make_layout(const Sizes &s) {
   const size_t radix_blocks = std::max<size_t>((items + 2047) / 2048, 1);
   const size_t scan_words = std::max<size_t>(std::max<size_t>(256 * radix_blocks, s.cap_rec), (size_t)s.t_tot + 1);
   put(L.scalars, kNumScalars * 4);
+  put(L.queues, 2 * kQueueLanes * kQueueStride * 4);
   put(L.tile_count, (size_t)s.t_tot * 4);
   put(L.tile_start, (size_t)s.t_tot * 4);
   L.zero_end = o;
@@ -334,6 +337,7 @@ gsr_status gsr_plan(gsr_ctx *c, const gsr_camera *cams, int32_t n_views, int64_t
   s.cap_pairs = (uint32_t)cap_pairs;
   s.n_blocks = (uint32_t)((n + kPreBlock - 1) / kPreBlock);
   s.long_list = c->long_list;
+  s.persistent = (uint32_t)c->persistent;
   s.vis_words = (uint32_t)((n_views + 63) / 64);
   for (int k = 0; k < 3; ++k) s.bg[k] = opt ? opt->bg[k] : 0.0f;
   c->views = views;
@@ -633,8 +637,11 @@ gsr_status gsr_set_tuning(gsr_ctx *c, const gsr_tuning *t) {
   if (!t) return fail(c, GSR_ERR_INVALID_ARG, "tuning is NULL");
   if (t->tile_size != 8 && t->tile_size != 16 && t->tile_size != 32)
     return fail(c, GSR_ERR_INVALID_ARG, "tile size %d not in {8, 16, 32}", t->tile_size);
+  if (t->persistent != 0 && t->persistent != 1)
+    return fail(c, GSR_ERR_INVALID_ARG, "persistent %d not in {0, 1}", t->persistent);
   c->tuned_ts = t->tile_size;
   c->long_list = t->long_list;
+  c->persistent = t->persistent;
   return GSR_OK;
 }
 
@@ -643,6 +650,7 @@ gsr_status gsr_get_tuning(gsr_ctx *c, gsr_tuning *t) {
   if (!t) return fail(c, GSR_ERR_INVALID_ARG, "tuning is NULL");
   t->tile_size = c->tuned_ts;
   t->long_list = c->long_list;
+  t->persistent = c->persistent;
   t->step_ms = 0.0f;
   return GSR_OK;
 }

@@ -64,7 +64,7 @@ class Rasterizer:
 
     def __init__(self, cams: Sequence, n: int, sh_degree: int, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
                  capacity_records: int = 0, capacity_pairs: int = 0, device="cuda", cams_device=None,
-                 long_list: int = 1024):
+                 long_list: int = 1024, persistent: bool = False):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -86,7 +86,8 @@ class Rasterizer:
         # bumped by every call that rewrites the workspace's binning state (a
         # plan or a forward), so a backward can tell that its state is gone
         self.generation = 0
-        self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(self.tile_size or 16, long_list, 0.0))))
+        self._check(self.lib.gsr_set_tuning(
+            self.ctx, C.byref(L.Tuning(self.tile_size or 16, int(long_list), int(bool(persistent)), 0.0))))
         self._plan(capacity_records, capacity_pairs)
 
     # -- plan / workspace ------------------------------------------------------------------
@@ -109,11 +110,12 @@ class Rasterizer:
     def tuning(self):
         t = L.Tuning()
         self._check(self.lib.gsr_get_tuning(self.ctx, C.byref(t)))
-        return {"tile_size": t.tile_size, "long_list": t.long_list}
+        return {"tile_size": t.tile_size, "long_list": t.long_list, "persistent": bool(t.persistent)}
 
-    def set_tuning(self, tile_size, long_list=1024):
+    def set_tuning(self, tile_size, long_list=1024, persistent=False):
         """Change the launch configuration and re-plan (same capacities)."""
-        self._check(self.lib.gsr_set_tuning(self.ctx, C.byref(L.Tuning(int(tile_size), int(long_list), 0.0))))
+        self._check(self.lib.gsr_set_tuning(
+            self.ctx, C.byref(L.Tuning(int(tile_size), int(long_list), int(bool(persistent)), 0.0))))
         self.tile_size = int(tile_size)
         self._plan(*self.capacity)
 
@@ -131,7 +133,8 @@ class Rasterizer:
         self.tile_size = best.tile_size if status == 0 else self.tile_size
         self._plan(*self.capacity)
         self._check(status)
-        return {"tile_size": best.tile_size, "long_list": best.long_list, "step_ms": best.step_ms}
+        return {"tile_size": best.tile_size, "long_list": best.long_list, "persistent": bool(best.persistent),
+                "step_ms": best.step_ms}
 
     def _check(self, status):
         L.check(self.ctx, status)

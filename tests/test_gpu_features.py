@@ -132,9 +132,10 @@ def test_backward_is_deterministic():
         assert torch.equal(a[k], b[k]), k
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replays_match_eager(persistent):
     scene_, cams = make_config(3, scale=0.005)
-    rast, params, _ = render_gpu(scene_, cams)
+    rast, params, _ = render_gpu(scene_, cams, persistent=persistent)
     out = rast.new_fwd_out()
     dl = torch.from_numpy(np.random.default_rng(2).standard_normal(3 * rast.total_px).astype(np.float32)).cuda()
     grads = {k: torch.empty_like(v) for k, v in params.items()}
@@ -250,7 +251,7 @@ def test_abi_rejects_invalid_arguments(cfg1):
     st = lib.gsr_render_forward(rast2.ctx, C.byref(g), C.c_void_p(rast2.cams_dev.data_ptr()), 1,
                                 C.c_void_p(rast2.workspace.data_ptr()), rast2.ws_bytes, C.byref(fo), rast2.stream())
     assert st == L.GSR_ERR_NOT_PLANNED
-    assert lib.gsr_set_tuning(rast2.ctx, C.byref(L.Tuning(12, 512, 0.0))) == L.GSR_ERR_INVALID_ARG
+    assert lib.gsr_set_tuning(rast2.ctx, C.byref(L.Tuning(12, 512, 0, 0.0))) == L.GSR_ERR_INVALID_ARG
 
 
 def _edge_check(sc, cams, ts=16):
