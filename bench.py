@@ -90,8 +90,8 @@ def stage_work(stage, n, n_u, pg, views, px, rec, pairs, tiles, evals):
         return 40 * pairs + 20 * px, BWD_OPS_PER_EVAL * evals
     if stage == "reduce":       # per-record 2D gradients out and back in
         return 72 * rec, 0
-    if stage == "pre_bwd":      # 2D grads + params in; Adam p, m, v in and out
-        return 36 * rec + 4 * pg * (n_u + n) + 28 * pg * n, 0
+    if stage == "pre_bwd":      # 2D grads in; Adam fused: each parameter read once, its moments
+        return 36 * rec + 24 * pg * n + 4 * n, 0  # read, all three written (no gradient array)
     return 0, 0
 
 

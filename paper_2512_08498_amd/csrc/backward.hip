@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   bool seen = false;
   const uint32_t r0 = ws.rec_start[g], r1 = ws.rec_start[g + 1];
 
-  // pass 1: geometry, opacity, and the colour's dependence on the direction
+  // pass 1: geometry and opacity (the colour's dependence on the direction
+  // is added in pass 2, where the SH coefficients are in registers)
   for (uint32_t r = r0; r < r1; ++r) {
     const int v = (int)ws.rec_view[r];
     const Cam c = load_cam(cams, v);
@@ -93,26 +94,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float d_offx = ga.x, d_offy = ga.y, d_qa = ga.z, d_qb = ga.w, d_qc = gb.x;
     d_op += gb.y;
 
-    if (DEG > 0) {
-      float cc[3], d[3], inv;
-      colour_cot(ws, r, cc);
-      view_dir(c, m3, d, inv);
-      float w[16];
-      w[0] = 0.0f;
-#pragma unroll
-      for (int k = 1; k < K; ++k) {
-        const int64_t base = (int64_t)k * 3 * n + g;
-        w[k] = cc[0] * gp.sh[base] + cc[1] * gp.sh[base + n] + cc[2] * gp.sh[base + 2 * n];
-      }
-#pragma unroll
-      for (int k = K; k < 16; ++k) w[k] = 0.0f;
-      float gd[3];
-      sh_grad_dot(d[0], d[1], d[2], DEG, w, gd);
-      const float dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-      d_mean[0] += (gd[0] - dot * d[0]) * inv;
-      d_mean[1] += (gd[1] - dot * d[1]) * inv;
-      d_mean[2] += (gd[2] - dot * d[2]) * inv;
-    }
 
     // conic (Cholesky form) -> 2D covariance
     const float syy = P.p1 + kDilation;
@@ -221,11 +202,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float bc1 = 1.0f, bc2 = 1.0f;
   if (ADAM) bias_corrections(adam, bc1, bc2);
   // Gradients of a group of N parameters (pointer offsets off[i] from the
-  // group's arrays): written out, or applied by Adam with all loads of the
-  // group issued before any store, so the memory latency is paid once per
-  // group rather than once per parameter.
+  // group's arrays) whose current values pv the thread already holds:
+  // written out, or applied by Adam with all loads of the group issued
+  // before any store, so the memory latency is paid once per group rather
+  // than once per parameter.
   auto emit_group = [&](auto tag, float *p, float *m, float *v, float *gout, const int64_t(&off)[decltype(tag)::N],
-                        const float(&gv)[decltype(tag)::N], const float(&lr)[decltype(tag)::N]) {
+                        const float(&pv)[decltype(tag)::N], const float(&gv)[decltype(tag)::N],
+                        const float(&lr)[decltype(tag)::N]) {
     constexpr int N = decltype(tag)::N;
     if (!ADAM) {
 #pragma unroll
@@ -235,7 +218,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     float pp[N], mm[N], vv[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      pp[i] = p[off[i]];
+      pp[i] = adam.p_is_g ? pv[i] : p[off[i]];
       mm[i] = m[off[i]];
       vv[i] = v[off[i]];
     }
@@ -249,53 +232,85 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (gout) gout[off[i]] = gv[i];
     }
   };
+
+  // the view-independent groups, from the values loaded at the start
   {
     const int64_t o3[3] = {g, n + g, 2 * n + g}, o4[4] = {g, n + g, 2 * n + g, 3 * n + g}, o1[1] = {g};
-    const float lr0[3] = {adam.lr[0], adam.lr[0], adam.lr[0]}, lr1[3] = {adam.lr[1], adam.lr[1], adam.lr[1]};
+    const float lr1[3] = {adam.lr[1], adam.lr[1], adam.lr[1]};
     const float lr2[4] = {adam.lr[2], adam.lr[2], adam.lr[2], adam.lr[2]}, lr3[1] = {adam.lr[3]};
-    const float gth[1] = {d_theta};
-    emit_group(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, o3, d_mean, lr0);
-    emit_group(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, o3, d_l, lr1);
-    emit_group(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, o4, d_q, lr2);
+    const float gth[1] = {d_theta}, th[1] = {theta};
+    emit_group(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, o3, l3, d_l, lr1);
+    emit_group(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, o4, q4, d_q, lr2);
     emit_group(GroupN<1>{}, adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit,
-               o1, gth, lr3);
+               o1, th, gth, lr3);
   }
 
-  // pass 2: SH coefficients, all K x 3 sums in one walk over the records
-  // (the geometry registers are dead by now), then the updates in groups of
-  // two coefficients (six parameters)
-  float a[K][3];
+  // pass 2: the SH coefficients, loaded once (the values the Adam update
+  // starts from too), and one walk over the records for the colour's
+  // dependence on the viewing direction and the coefficients' gradient sums;
+  // those sums sit in this thread's column of LDS (registers would spill),
+  // then the updates go in groups of two coefficients (six parameters)
+  float shv[K][3];
 #pragma unroll
-  for (int k = 0; k < K; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0f;
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) shv[k][ch] = gp.sh[((int64_t)k * 3 + ch) * n + g];
+  __shared__ float a_lds[3 * K][256];
+  const int tc = (int)threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) a_lds[i][tc] = 0.0f;
+  float d_dir[3] = {0.f, 0.f, 0.f};
   for (uint32_t r = r0; r < r1; ++r) {
     const Cam c = load_cam(cams, (int)ws.rec_view[r]);
     float cc[3], d[3], inv;
     colour_cot(ws, r, cc);
     view_dir(c, m3, d, inv);
-    float Y[16];
-    sh_basis(d[0], d[1], d[2], DEG, Y);
+    {
+      float Y[16];
+      sh_basis(d[0], d[1], d[2], DEG, Y);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      a[k][0] += Y[k] * cc[0];
-      a[k][1] += Y[k] * cc[1];
-      a[k][2] += Y[k] * cc[2];
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) a_lds[3 * k + ch][tc] += Y[k] * cc[ch];
+    }
+    if (DEG > 0) {
+      float w[16];
+      w[0] = 0.0f;
+#pragma unroll
+      for (int k = 1; k < K; ++k) w[k] = cc[0] * shv[k][0] + cc[1] * shv[k][1] + cc[2] * shv[k][2];
+#pragma unroll
+      for (int k = K; k < 16; ++k) w[k] = 0.0f;
+      float gd[3];
+      sh_grad_dot(d[0], d[1], d[2], DEG, w, gd);
+      const float dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+      d_dir[0] += (gd[0] - dot * d[0]) * inv;
+      d_dir[1] += (gd[1] - dot * d[1]) * inv;
+      d_dir[2] += (gd[2] - dot * d[2]) * inv;
     }
   }
   constexpr int KC = K < 2 ? K : 2;
 #pragma unroll
   for (int kc = 0; kc < K; kc += KC) {
     int64_t off[3 * KC];
-    float gv[3 * KC], lr[3 * KC];
+    float pv[3 * KC], gv[3 * KC], lr[3 * KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         const int k = kc + kk;
         off[3 * kk + ch] = ((int64_t)k * 3 + ch) * n + g;
-        gv[3 * kk + ch] = a[k][ch];
+        pv[3 * kk + ch] = shv[k][ch];
+        gv[3 * kk + ch] = a_lds[3 * k + ch][tc];
         lr[3 * kk + ch] = k == 0 ? adam.lr[4] : adam.lr[5];
       }
-    emit_group(GroupN<3 * KC>{}, adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, off, gv, lr);
+    emit_group(GroupN<3 * KC>{}, adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, off, pv, gv, lr);
+  }
+  // the mean's update, now that the direction term is in
+  {
+    const float dm[3] = {d_mean[0] + d_dir[0], d_mean[1] + d_dir[1], d_mean[2] + d_dir[2]};
+    const int64_t o3[3] = {g, n + g, 2 * n + g};
+    const float lr0[3] = {adam.lr[0], adam.lr[0], adam.lr[0]};
+    emit_group(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, o3, m3, dm, lr0);
   }
 }
 

@@ -56,6 +56,7 @@ struct AdamArgs {
   float lr[6];
   float beta1, beta2, eps;
   int32_t *step;
+  int32_t p_is_g;  // the parameters p are the rendered Gaussians' own arrays (values already loaded)
 };
 
 void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);

@@ -530,6 +530,8 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   if (st != GSR_OK) return st;
   AdamArgs a{};
   if ((st = adam_args(c, params, m, v, cfg, step_dev, a)) != GSR_OK) return st;
+  a.p_is_g = a.p.mean == g->mean && a.p.log_scale == g->log_scale && a.p.quat == g->quat &&
+             a.p.opacity_logit == g->opacity_logit && a.p.sh == g->sh;
   MutPtrs gr{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (grads_out) {
     gr = mut_ptrs(grads_out);

@@ -1,5 +1,6 @@
 """GPU tests of the loss, the optimiser, invariances, the sort size classes,
 capacity handling and edge cases (all through the C ABI)."""
+import ctypes as C
 import math
 
 import numpy as np
@@ -88,6 +89,34 @@ def test_fused_backward_adam_equals_backward_then_adam():
         assert torch.equal(g_out[k], grads[k]), k
         assert torch.allclose(p1[k], p2[k], rtol=0, atol=1e-7), k
         assert torch.equal(opt1.m[k], opt2.m[k]), k
+
+
+def test_fused_adam_into_separate_parameter_arrays():
+    """The fused step may update parameter arrays other than the rendered
+    Gaussians' own (holding the same values): the result equals the
+    in-place update bit for bit, so the kernel's reuse of the values it has
+    already loaded is only taken when the arrays are the same."""
+    scene_, cams = mini_rig()
+    rng = np.random.default_rng(6)
+    rast, params, out = render_gpu(scene_, cams)
+    dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-4).cuda()
+    p_in = {k: v.clone() for k, v in params.items()}
+    opt_in = FusedAdam(rast, p_in)
+    rast.backward_adam(p_in, out, dl, opt_in)
+    p_sep = {k: v.clone() for k, v in params.items()}
+    opt_sep = FusedAdam(rast, p_sep)
+    lib = rast.lib
+    st = lib.gsr_render_backward_adam(
+        rast.ctx, C.byref(rast._gaussians(params)), C.c_void_p(rast.cams_dev.data_ptr()), rast.views,
+        C.c_void_p(rast.workspace.data_ptr()), rast.ws_bytes, C.byref(rast._fwd_struct(out)),
+        C.c_void_p(dl.data_ptr()), C.byref(opt_sep.param_struct(p_sep)), C.byref(opt_sep.m_struct()),
+        C.byref(opt_sep.v_struct()), C.byref(opt_sep.config), C.c_void_p(opt_sep.step.data_ptr()), None,
+        rast.stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        assert torch.equal(p_in[k], p_sep[k]), k
+        assert torch.equal(opt_in.m[k], opt_sep.m[k]) and torch.equal(opt_in.v[k], opt_sep.v[k]), k
 
 
 def test_forward_bitwise_invariant_to_tile_size_and_repeatable(cfg1):
