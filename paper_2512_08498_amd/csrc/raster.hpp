@@ -78,18 +78,21 @@ __device__ __forceinline__ bool tile_reaches(const float4 box, const float4 p1, 
 // Which staged records each 8 x 8 pixel block of the calling thread's wave
 // can composite.  Every pixel mapping of the compositing kernels gives a wave
 // one 8 x 8 block per pixel slot p, lane l at (l & 7, l >> 3) within it, so
-// the block origin is the pixel of the wave's lane 0.  mk[p][c] bit b: the
-// compositing box of batch record 64 c + b (c < NC, 64 c + b < m) meets
-// block p.  Outside that box alpha < 1/255 at every pixel centre (the box is
-// the alpha >= 1/255 region's bounding box, with a margin), so a record
-// whose bit is clear composites nowhere in the block, and within a block the
-// per-pixel alpha test alone decides.  The masks are wave-uniform, so the
-// record loops branch on them in scalar registers and skip records without
-// touching LDS.  Every thread of the group must call this after the batch's
-// payloads p0 (boxes) are in LDS.
-template <int PPT, int NC, class Pix>
-__device__ __forceinline__ void block_masks(const float4 *p0, uint32_t m, int t, float ox, float oy, Pix pix,
-                                            uint64_t (&mk)[PPT][NC]) {
+// the block origin is the pixel of the wave's lane 0.  mk[p][c] bit b: batch
+// record 64 c + b (c < NC, 64 c + b < m) may composite in block p.  Outside
+// the record's compositing box alpha < 1/255 at every pixel centre (the box
+// is the alpha >= 1/255 region's bounding box, with a margin); with ELLIPSE
+// the block must also pass the exact test of tile_reaches (the falloff's
+// minimum over block ∩ box against the threshold, with its rounding margin),
+// which drops the blocks in the corners of a tilted or elongated footprint's
+// box.  Both tests are conservative, so a record whose bit is clear
+// composites nowhere in the block, and within a block the per-pixel alpha
+// test alone decides.  The masks are wave-uniform, so the record loops branch
+// on them in scalar registers and skip records without touching LDS.  Every
+// thread of the group must call this after the batch's payloads are in LDS.
+template <int PPT, int NC, bool ELLIPSE, class Pix>
+__device__ __forceinline__ void block_masks(const float4 *p0, const float4 *p1, const float4 *p2, uint32_t m, int t,
+                                            float ox, float oy, Pix pix, uint64_t (&mk)[PPT][NC]) {
   float bx[PPT], by[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -103,9 +106,15 @@ __device__ __forceinline__ void block_masks(const float4 *p0, uint32_t m, int t,
     const uint32_t j = (uint32_t)(c * kWave + lane_id());
     const bool live = j < m;
     const float4 b = p0[live ? j : 0u];
+    if (!ELLIPSE) {
 #pragma unroll
-    for (int p = 0; p < PPT; ++p)
-      mk[p][c] = __ballot(live & (b.x <= bx[p] + 7.0f) & (b.y >= bx[p]) & (b.z <= by[p] + 7.0f) & (b.w >= by[p]));
+      for (int p = 0; p < PPT; ++p)
+        mk[p][c] = __ballot(live & (b.x <= bx[p] + 7.0f) & (b.y >= bx[p]) & (b.z <= by[p] + 7.0f) & (b.w >= by[p]));
+    } else {
+      const float4 q1 = p1[live ? j : 0u], q2 = p2[live ? j : 0u];
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) mk[p][c] = __ballot(live && tile_reaches(b, q1, q2, bx[p], by[p], 8.0f));
+    }
   }
 }
 

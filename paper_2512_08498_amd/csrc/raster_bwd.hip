@@ -188,7 +188,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
     // blocks, and there only the pixels in front of their stored end
     constexpr int NC = (B + kWave - 1) / kWave;
     uint64_t mk[PPT][NC];
-    block_masks<PPT, NC>(L.p0, mc, t, ox, oy, pix, mk);
+    block_masks<PPT, NC, false>(L.p0, L.p1, L.p2, mc, t, ox, oy, pix, mk);
 #pragma unroll
     for (int c = NC - 1; c >= 0; --c) {
       uint64_t rem = 0;

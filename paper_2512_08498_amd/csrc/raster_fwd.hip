@@ -105,7 +105,7 @@ __device__ __forceinline__ void fwd_walk(const ViewInfo *__restrict__ views, con
     // only the records that can composite in one of its blocks
     constexpr int NC = (B + kWave - 1) / kWave;
     uint64_t mk[PPT][NC];
-    block_masks<PPT, NC>(L.p0, m, t, (float)(tx * TS), (float)(ty * TS), pix, mk);
+    block_masks<PPT, NC, true>(L.p0, L.p1, L.p2, m, t, (float)(tx * TS), (float)(ty * TS), pix, mk);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       uint64_t any = 0;
