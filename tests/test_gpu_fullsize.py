@@ -81,3 +81,26 @@ def test_fullsize_window_gradients(rig):
         log(f"  grad {k}: {diff.max() / scale:.2e} of max, rel {rel:.2e}")
         assert diff.max() <= 1e-4 * scale, k
         assert rel <= 1e-4, k
+
+
+def test_fullsize_persistent_schedule_bitwise(rig):
+    """The persistent compositing schedule at full size gives the grid
+    schedule's images, stop positions, counts and gradients bit for bit."""
+    from paper_2512_08498_amd import Rasterizer
+
+    scene, cams, rast, params, out = rig
+    rng = np.random.default_rng(77)
+    dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-6).cuda()
+    res = []
+    for pers in (False, True):
+        r = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=16, persistent=pers,
+                       capacity_records=rast.capacity[0], capacity_pairs=rast.capacity[1])
+        o = r.forward(params)
+        g = r.backward(params, o, dl)
+        torch.cuda.synchronize()
+        res.append({**{k: o[k].cpu().numpy() for k in ("image", "t_final", "last_pos", "n_contrib")},
+                    **{"g_" + k: v.cpu().numpy() for k, v in g.items()}})
+        log(f"persistent={pers} done")
+        del r, o, g
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
