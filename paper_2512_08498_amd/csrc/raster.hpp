@@ -1,10 +1,12 @@
 // Tile geometry shared by the forward and backward compositing kernels.
 //
 // A tile of TS x TS pixels is walked by one workgroup, or at 16 px by one
-// wave of it, taken from a work queue by a persistent launch.  Records are staged
-// in LDS in batches and read back as broadcasts; a record whose pixel box
-// misses a lane's pixel costs only the box test (the per-lane test clears
-// the exec mask and the body is branched over).  The forward and the
+// wave of it: one workgroup per work item, or (a tuning option) persistent
+// workgroups taking items from a work queue.  Records are staged in LDS in
+// batches and read back as broadcasts; per 8 x 8 pixel block a wave visits
+// only the records whose box (in the forward, whose falloff) can reach it
+// (block_masks), so a record that misses a block costs nothing there.  The
+// forward and the
 // backward split a tile differently (FwdTile / TileCfg below): the forward
 // spreads a tile over four waves (one pixel per lane), the backward keeps a
 // 16 x 16 block in one wave (four pixels per lane) so the per-record wave
@@ -208,12 +210,14 @@ __device__ __forceinline__ void pixel_of(int t, int p, int &x, int &y) {
 // (on a 128-byte line of its own) is used from one XCD: the eight are served
 // in parallel, where a single counter for all workgroups serialised the
 // atomics and doubled the compositing time.  The add for the next item is
-// issued when the current one starts, so its latency is hidden behind the
-// walk.  A workgroup stops at its first item past the end; the claim it
-// still has in flight then lies past the end too (a lane's items grow with
-// its count), so no item is lost.  The counters start at zero: the
-// forward's first kernel zeroes both queues, and the pair reduction that
-// follows every compositing backward zeroes the backward's again.
+// issued when the current one starts (a wave's memory returns complete in
+// order, so it is still waited for at the walk's first load, which overlaps
+// most of its latency).  A workgroup stops at its first item past the end;
+// the claim it still has in flight then lies past the end too (a lane's
+// items grow with its count), so no item is lost.  The counters start at
+// zero: the forward's first kernel zeroes both queues, and the pair
+// reduction that follows every compositing backward zeroes the backward's
+// again.
 // Without persistence (P = false) the grid has one workgroup per item and
 // next() ends the walk after the first; the kernels are instantiated for
 // both, so the grid schedule carries no queue state.
