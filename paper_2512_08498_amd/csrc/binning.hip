@@ -56,7 +56,7 @@ __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t 
 // whole wave, 64 pairs per step.
 constexpr uint32_t kEmitSmall = 8;
 
-__global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views, Ws ws, Sizes sz,
+__global__ __launch_bounds__(256) void k_emit(Ws ws, Sizes sz,
                                               const uint32_t *__restrict__ perm, const uint32_t *__restrict__ offs,
                                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   if (ws.scalars[kOverflow]) return;
@@ -69,15 +69,14 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo *__restrict__ views
     uint32_t tx0 = 0, tx1 = 0, ty0 = 0, w = 1, cnt = 0, off = 0, rec = 0, tbase = 0, tpitch = 0;
     if (i < nrec) {
       rec = perm[i];
-      const uint2 rc = ws.rec_rect[rec];
+      const uint4 rc = ws.rec_rect[rec];  // one gather: rectangle, first tile, row pitch
       tx0 = rc.x & 0xFFFFu;
       tx1 = rc.x >> 16;
       ty0 = rc.y & 0xFFFFu;
       w = tx1 - tx0 + 1;
       cnt = w * ((rc.y >> 16) - ty0 + 1);
-      const ViewInfo vi = views[ws.rec_view[rec]];
-      tbase = vi.tile_base;
-      tpitch = (uint32_t)vi.tiles_x;
+      tbase = rc.z - ty0 * rc.w - tx0;  // so that tbase + ty * pitch + tx is the tile's id
+      tpitch = rc.w;
       off = offs[i];
       if (off + cnt > sz.cap_pairs) {  // inconsistent pair offsets
         ws.scalars[kOverflow] = 3u;
@@ -285,7 +284,7 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
                                                           uint32_t *__restrict__ vals_out,
                                                           const uint32_t *__restrict__ count_dev, uint32_t cap,
                                                           int shift, const uint32_t *__restrict__ hist,
-                                                          const uint2 *__restrict__ rect,
+                                                          const uint4 *__restrict__ rect,
                                                           uint32_t *__restrict__ area_out) {
   constexpr int NW = kRdxNT / kWave;
   constexpr uint32_t CHUNK = kRdxNT * IPL;
@@ -358,7 +357,7 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
       keys_out[g] = k;
       vals_out[g] = v;
       if (area_out) {  // tile-rectangle area of record v
-        const uint2 rc = rect[v];
+        const uint4 rc = rect[v];
         area_out[g] = ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
       }
     }
@@ -504,7 +503,7 @@ void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStr
   uint32_t *kb = reinterpret_cast<uint32_t *>(ws.partials), *vb = kb + sz.cap_pairs;
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
-  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(views, ws, sz, perm, offs, ka, va);
+  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(ws, sz, perm, offs, ka, va);
   const int bits = std::max(1, bit_width(sz.t_tot - 1));
   const int passes = (bits + 7) / 8;
   // the last pass reads (kb, vb) when the pass count is even, else (ka, va)

@@ -48,7 +48,8 @@ struct Ws {
   uint32_t *rec_g;          // [cap_rec] Gaussian index
   uint32_t *rec_view;       // [cap_rec] view index
   uint32_t *rec_pairoff;    // [cap_rec] first gradient slot of the record (records in order, tiles row-major)
-  uint2 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  uint4 *rec_rect;          // [cap_rec] (tx0 | tx1 << 16, ty0 | ty1 << 16, global id of tile (tx0, ty0),
+                            //   tiles per row of the view): one 16-byte line part per record
   uint32_t *rec_zbits;      // [cap_rec] depth bits
   uint32_t *rec_tmp;        // [5][cap_rec] depth sort of the records, pair offsets
   uint32_t *tile_order;     // [T_tot] tiles by decreasing list length

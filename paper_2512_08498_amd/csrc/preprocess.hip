@@ -193,7 +193,8 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Ws ws, Sizes sz) {
 }
 
 template <int DEG>
-__global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam *__restrict__ cams, Ws ws,
+__global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam *__restrict__ cams,
+                                                         const ViewInfo *__restrict__ views, Ws ws,
                                                          Sizes sz, int ts_shift) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t s_scan[kPreBlock / kWave * 2];
@@ -298,7 +299,10 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
       const int ty0 = P.j0 >> ts_shift, ty1 = P.j1 >> ts_shift;
       ws.rec_g[rec] = (uint32_t)g;
       ws.rec_view[rec] = (uint32_t)v;
-      ws.rec_rect[rec] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+      const ViewInfo vi = views[v];
+      ws.rec_rect[rec] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
+                                    vi.tile_base + (uint32_t)ty0 * (uint32_t)vi.tiles_x + (uint32_t)tx0,
+                                    (uint32_t)vi.tiles_x);
       ws.rec_zbits[rec] = P.zbits;
       pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
       rec += 1;
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(kPreBlock) void k_pre_write(GaussPtrs gp, const Cam
   uint32_t slot = base.y + block_excl_scan<kPreBlock>(pairs, s_scan + kPreBlock / kWave, tp);
   if (live)
     for (uint32_t r = rec0; r < rec0 + recs; ++r) {
-      const uint2 rc = ws.rec_rect[r];
+      const uint4 rc = ws.rec_rect[r];
       ws.rec_pairoff[r] = slot;
       slot += ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
     }
@@ -321,8 +325,7 @@ void launch_zero(uint32_t *p, uint64_t n_words, hipStream_t st);
 
 void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *views, const Ws &ws,
                        const Sizes &sz, int sh_degree, uint32_t *zero, uint64_t n_zero, hipStream_t st) {
-  (void)views;
-  const int ts_shift = sz.ts == 8 ? 3 : (sz.ts == 16 ? 4 : 5);
+    const int ts_shift = sz.ts == 8 ? 3 : (sz.ts == 16 ? 4 : 5);
   if (sz.n_blocks == 0) {
     launch_zero(zero, n_zero, st);
     return;
@@ -330,10 +333,10 @@ void launch_preprocess(const GaussPtrs &gp, const Cam *cams, const ViewInfo *vie
   k_pre_count<<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift, zero, n_zero);
   k_scan_blocks<<<1, 1024, 0, st>>>(ws, sz);
   switch (sh_degree) {
-    case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
-    case 1: k_pre_write<1><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
-    case 2: k_pre_write<2><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
-    default: k_pre_write<3><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, ws, sz, ts_shift); break;
+    case 0: k_pre_write<0><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    case 1: k_pre_write<1><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    case 2: k_pre_write<2><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
+    default: k_pre_write<3><<<sz.n_blocks, kPreBlock, 0, st>>>(gp, cams, views, ws, sz, ts_shift); break;
   }
 }
 

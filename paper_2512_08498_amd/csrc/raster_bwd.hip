@@ -118,7 +118,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       ws.scalars[kOverflow] = 4u;
       rec = 0;
     }
-    const uint2 rc = ws.rec_rect[rec];
+    const uint4 rc = ws.rec_rect[rec];
     const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
     if (tx < tx0 || tx > tx1 || ty < ty0 || ty > ty1) {  // not this record's tile: corrupt list
       ws.scalars[kOverflow] = 4u;
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
     const uint32_t r = wbase + lane;
     uint32_t cnt = 0, p0 = 0;
     if (r < nrec) {
-      const uint2 rc = ws.rec_rect[r];
+      const uint4 rc = ws.rec_rect[r];
       cnt = ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
       p0 = ws.rec_pairoff[r];
     }

@@ -117,7 +117,7 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   w.rec_g = reinterpret_cast<uint32_t *>(b + L.rec_g);
   w.rec_view = reinterpret_cast<uint32_t *>(b + L.rec_view);
   w.rec_pairoff = reinterpret_cast<uint32_t *>(b + L.rec_pairoff);
-  w.rec_rect = reinterpret_cast<uint2 *>(b + L.rec_rect);
+  w.rec_rect = reinterpret_cast<uint4 *>(b + L.rec_rect);
   w.rec_zbits = reinterpret_cast<uint32_t *>(b + L.rec_zbits);
   w.tile_count = reinterpret_cast<uint32_t *>(b + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t *>(b + L.tile_start);
@@ -158,7 +158,7 @@ Layout make_layout(const Sizes &s) {
   put(L.rec_g, (size_t)s.cap_rec * 4);
   put(L.rec_view, (size_t)s.cap_rec * 4);
   put(L.rec_pairoff, (size_t)s.cap_rec * 4);
-  put(L.rec_rect, (size_t)s.cap_rec * 8);
+  put(L.rec_rect, (size_t)s.cap_rec * 16);
   put(L.rec_zbits, (size_t)s.cap_rec * 4);
   put(L.rec_tmp, (size_t)s.cap_rec * 20);
   put(L.tile_order, (size_t)s.t_tot * 4);
