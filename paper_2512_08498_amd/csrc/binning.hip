@@ -1,5 +1,5 @@
 // Depth sort and tile binning, as stable counting (LSD radix) passes on
-// 8-bit digits -- no global atomics on contended addresses:
+// 8- to 10-bit digits -- no global atomics on contended addresses:
 //
 //  sort      the visible records by their depth bits (four passes; stable,
 //            so equal depths keep record order, which is Gaussian order
@@ -7,13 +7,14 @@
 //  emission  every (record, tile) pair in depth-sorted record order: the
 //            global tile id as key, the record as value, at the record's
 //            pair offset (a scan of the rectangle areas in that order);
-//  tile sort the pairs by tile id (two or three passes): being stable, it
+//  tile sort the pairs by tile id (8-bit passes up to 2^16 tiles, two
+//            9- or 10-bit passes up to 2^20 tiles): being stable, it
 //            leaves each tile's list in (depth, record) order, the
 //            compositing order, so no per-tile sort is needed -- together
 //            the passes sort the 64-bit (tile | depth) keys;
 //  bounds    list start and length of every tile from the sorted ids;
-//  classify  the longest-first key of each tile; the longest-first tile
-//            order is two more passes over 16-bit keys.
+//  classify  the longest-first key of each tile (an 8-bit length code);
+//            the longest-first tile order is one more pass over it.
 //
 // A pass is a per-block digit histogram, a device-wide scan of the
 // histograms, and a scatter that ranks each block's items by digit with
@@ -48,16 +49,17 @@ __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t 
   return count_dev ? min(*count_dev, cap) : cap;
 }
 
-// Emission: each wave takes 64 consecutive records of the depth order; their
-// pairs form one contiguous range (offs[i] is the first pair of sorted record
-// i).  A record of at most kEmitSmall pairs is written by its own lane,
+// Emission: each wave takes 64 consecutive records of the depth order (their
+// indices perm[i] and tile records srect[i] are read in order); their pairs
+// form one contiguous range (offs[i] is the first pair of sorted record i).  A record of at most kEmitSmall pairs is written by its own lane,
 // stepping through its tile rectangle; the lanes' stores fall into that one
 // range.  Bigger footprints are written by the
 // whole wave, 64 pairs per step.
 constexpr uint32_t kEmitSmall = 8;
 
 __global__ __launch_bounds__(256) void k_emit(Ws ws, Sizes sz,
-                                              const uint32_t *__restrict__ perm, const uint32_t *__restrict__ offs,
+                                              const uint32_t *__restrict__ perm, const uint4 *__restrict__ srect,
+                                              const uint32_t *__restrict__ offs,
                                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   if (ws.scalars[kOverflow]) return;
   const uint32_t nrec = ws.scalars[kNumRecords];
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, Sizes sz,
     uint32_t tx0 = 0, tx1 = 0, ty0 = 0, w = 1, cnt = 0, off = 0, rec = 0, tbase = 0, tpitch = 0;
     if (i < nrec) {
       rec = perm[i];
-      const uint4 rc = ws.rec_rect[rec];  // one gather: rectangle, first tile, row pitch
+      const uint4 rc = srect[i];  // rectangle, first tile, row pitch
       tx0 = rc.x & 0xFFFFu;
       tx1 = rc.x >> 16;
       ty0 = rc.y & 0xFFFFu;
@@ -110,51 +112,77 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, Sizes sz,
   }
 }
 
-// Lanes of the wave whose digit equals this lane's (8 ballots), among `live`.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool live) {
-  uint64_t eq = __ballot(live);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    eq &= bit ? m : ~m;
-  }
-  return eq;
+// Chunk of a counting-pass workgroup, given the number of chunks holding
+// live items.  Workgroups go to the 8 XCDs in turn, so the live chunks are
+// dealt out as 8 contiguous ranges, one per XCD: neighbouring chunks then
+// share the cache lines of their digit-major histogram entries, and of their
+// short digit runs in the output, in one XCD's L2 instead of writing parts
+// of the same lines from different XCDs.  Chunks past the live ones keep
+// their workgroup's index.
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t live_chunks) {
+  const uint32_t b = blockIdx.x;
+  if (b >= live_chunks) return b;
+  const uint32_t x = b & 7u, q = live_chunks >> 3, r = live_chunks & 7u;
+  return x * q + min(x, r) + (b >> 3);
 }
 
-// 2a. Digit histogram of one block's chunk (IPL items per lane), stored
-// digit-major: hist[d * gridDim.x + block].  Each wave loads its items
-// first, then counts them 64 at a time with one LDS atomic per distinct
-// digit.
-template <int IPL>
+// Lanes of the wave whose BITS-bit digit equals this lane's, among `live`:
+// one ballot per bit; a lane differs from this one where the ballot of some
+// bit differs from this lane's own bit (spread over a word as 0 or ~0), and
+// those differences are OR-ed up per 32-lane half.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool live) {
+  uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+    const uint64_t m = __ballot(x != 0u);
+    lo |= (uint32_t)m ^ x;
+    hi |= (uint32_t)(m >> 32) ^ x;
+  }
+  return ((uint64_t)~hi << 32 | (uint64_t)~lo) & __ballot(live);
+}
+
+// 2a. Digit histogram of one block's chunk (IPL items per lane) for digits
+// of BITS bits (8, 9 or 10: 2^BITS bins), stored digit-major:
+// hist[d * gridDim.x + chunk].  Each wave loads its items first, then counts
+// them 64 at a time: one LDS atomic when all 64 share a digit (as the high
+// depth bits mostly do), else one per lane.
+template <int IPL, int BITS>
 __global__ __launch_bounds__(kRdxNT) void k_digit_hist(const uint32_t *__restrict__ scalars,
                                                        const uint32_t *__restrict__ keys,
                                                        const uint32_t *__restrict__ count_dev, uint32_t cap,
                                                        int shift, uint32_t *__restrict__ hist) {
   constexpr uint32_t CHUNK = kRdxNT * IPL;
-  __shared__ uint32_t h[256];
+  constexpr uint32_t RADIX = 1u << BITS, MASK = RADIX - 1u;
+  __shared__ uint32_t h[RADIX];
   const uint32_t t = threadIdx.x;
-  h[t] = 0u;
+  for (uint32_t d = t; d < RADIX; d += kRdxNT) h[d] = 0u;
+  const uint32_t n = n_items(count_dev, cap);
+  const uint32_t c = xcd_chunk(n / CHUNK + (n % CHUNK != 0u));
   __syncthreads();
   if (!scalars[kOverflow]) {
-    const uint32_t n = n_items(count_dev, cap);
-    const uint32_t lo = blockIdx.x * CHUNK + (uint32_t)wave_id() * (CHUNK / 4) + (uint32_t)lane_id();
+    const uint32_t lo = c * CHUNK + (uint32_t)wave_id() * (CHUNK / 4) + (uint32_t)lane_id();
     uint32_t d[IPL];
 #pragma unroll
     for (int r = 0; r < IPL; ++r) {
       const uint32_t i = lo + (uint32_t)r * kWave;
-      d[r] = i < n ? (keys[i] >> shift) & 0xFFu : 0u;
+      d[r] = i < n ? (keys[i] >> shift) & MASK : 0u;
     }
-    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < IPL; ++r) {
-      const bool live = lo + (uint32_t)r * kWave < n;
-      const uint64_t eq = match_digit(d[r], live);
-      if (live && (eq & lt) == 0) atomicAdd(&h[d[r]], (uint32_t)__popcll(eq));
+      const bool live = lo + (uint32_t)r * kWave < n;  // lane 0 is live if any lane is
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d[r]);
+      const uint64_t all = __ballot(live);
+      if (__ballot(live && d[r] == d0) == all) {
+        if (lane_id() == 0 && all) atomicAdd(&h[d0], (uint32_t)__popcll(all));
+      } else if (live) {
+        atomicAdd(&h[d[r]], 1u);
+      }
     }
   }
   __syncthreads();
-  hist[t * gridDim.x + blockIdx.x] = h[t];
+  for (uint32_t d = t; d < RADIX; d += kRdxNT) hist[d * gridDim.x + c] = h[d];
 }
 
 // Device-wide exclusive scan of data[0, len): chunk sums, then each chunk
@@ -264,19 +292,20 @@ __global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *__restrict__ da
 // is needed per round.  The block then places its items in LDS in local
 // digit order (stable: waves and rounds in item order) and writes each
 // digit's run to its global offset, contiguously.  vals_in = NULL: the
-// values are the item indices.  With area_out, the values are records and
-// their tile-rectangle areas are written beside them.
-template <int IPL>
+// values are the item indices.  With area_out, the values are records, and
+// their tile-rectangle areas and tile records (rect_out) are written beside
+// them.
+template <int IPL, int BITS>
 struct ScatterLds {
   uint32_t key[kRdxNT * IPL];
   uint32_t val[kRdxNT * IPL];
-  uint32_t wcnt[kRdxNT / kWave][256];  // running, then starting, counts per wave and digit
-  uint32_t lstart[256];                // local start of each digit
-  uint32_t gbase[256];                 // global start of each digit for this block
+  uint32_t wcnt[kRdxNT / kWave][1u << BITS];  // running, then starting, counts per wave and digit
+  uint32_t lstart[1u << BITS];                // local start of each digit
+  uint32_t gbase[1u << BITS];                 // global start of each digit for this block
   uint32_t scan[kRdxNT / kWave];
 };
 
-template <int IPL>
+template <int IPL, int BITS>
 __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__restrict__ scalars,
                                                           const uint32_t *__restrict__ keys_in,
                                                           const uint32_t *__restrict__ vals_in,
@@ -285,20 +314,27 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
                                                           const uint32_t *__restrict__ count_dev, uint32_t cap,
                                                           int shift, const uint32_t *__restrict__ hist,
                                                           const uint4 *__restrict__ rect,
-                                                          uint32_t *__restrict__ area_out) {
+                                                          uint32_t *__restrict__ area_out,
+                                                          uint4 *__restrict__ rect_out) {
   constexpr int NW = kRdxNT / kWave;
   constexpr uint32_t CHUNK = kRdxNT * IPL;
-  __shared__ ScatterLds<IPL> S;
+  constexpr uint32_t RADIX = 1u << BITS, MASK = RADIX - 1u;
+  constexpr int DPT = (int)(RADIX / kRdxNT);  // digits per thread, consecutive: t * DPT + k
+  __shared__ ScatterLds<IPL, BITS> S;
   if (scalars[kOverflow]) return;
   const uint32_t t = threadIdx.x;
   const int w = wave_id(), lane = lane_id();
   const uint32_t n = n_items(count_dev, cap);
-  const uint32_t blo = blockIdx.x * CHUNK;
+  const uint32_t c = xcd_chunk(n / CHUNK + (n % CHUNK != 0u)), blo = c * CHUNK;
   if (blo >= n) return;  // uniform: nothing of this block is live
   const uint32_t m = min(CHUNK, n - blo);
 #pragma unroll
-  for (int k = 0; k < NW; ++k) S.wcnt[k][t] = 0u;
-  S.gbase[t] = hist[t * gridDim.x + blockIdx.x];
+  for (int e = 0; e < DPT; ++e) {
+    const uint32_t d = t * DPT + (uint32_t)e;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) S.wcnt[k][d] = 0u;
+    S.gbase[d] = hist[d * gridDim.x + c];
+  }
   const uint32_t lo = blo + (uint32_t)w * (CHUNK / NW);
   uint32_t key[IPL], val[IPL], rk[IPL];
 #pragma unroll
@@ -313,8 +349,8 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
   for (int r = 0; r < IPL; ++r) {
     const uint32_t i = lo + (uint32_t)r * kWave + (uint32_t)lane;
     const bool live = i < n;
-    const uint32_t d = (key[r] >> shift) & 0xFFu;
-    const uint64_t eq = match_digit(d, live);
+    const uint32_t d = (key[r] >> shift) & MASK;
+    const uint64_t eq = match_digit<BITS>(d, live);
     const uint32_t before = (uint32_t)__popcll(eq & lt);
     const uint32_t prior = S.wcnt[w][d];
     rk[r] = prior + before;
@@ -322,20 +358,27 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
   }
   __syncthreads();
   {
-    uint32_t c[NW], tot = 0;
+    // the thread's DPT consecutive digits: local starts in digit order, then
+    // per digit in wave order
+    uint32_t c[DPT][NW], tot = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      c[k] = S.wcnt[k][t];
-      tot += c[k];
-    }
+    for (int e = 0; e < DPT; ++e)
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        c[e][k] = S.wcnt[k][t * DPT + (uint32_t)e];
+        tot += c[e][k];
+      }
     uint32_t total;
-    const uint32_t ls = block_excl_scan<kRdxNT>(tot, S.scan, total);
-    S.lstart[t] = ls;
-    uint32_t run = ls;
+    uint32_t run = block_excl_scan<kRdxNT>(tot, S.scan, total);
 #pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      S.wcnt[k][t] = run;
-      run += c[k];
+    for (int e = 0; e < DPT; ++e) {
+      const uint32_t d = t * DPT + (uint32_t)e;
+      S.lstart[d] = run;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        S.wcnt[k][d] = run;
+        run += c[e][k];
+      }
     }
   }
   __syncthreads();
@@ -343,7 +386,7 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
   for (int r = 0; r < IPL; ++r) {
     const uint32_t i = lo + (uint32_t)r * kWave + (uint32_t)lane;
     if (i < n) {
-      const uint32_t p = S.wcnt[w][(key[r] >> shift) & 0xFFu] + rk[r];
+      const uint32_t p = S.wcnt[w][(key[r] >> shift) & MASK] + rk[r];
       S.key[p] = key[r];
       S.val[p] = val[r];
     }
@@ -351,14 +394,15 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
   __syncthreads();
   for (uint32_t j = t; j < m; j += kRdxNT) {
     const uint32_t k = S.key[j], v = S.val[j];
-    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t d = (k >> shift) & MASK;
     const uint32_t g = S.gbase[d] + (j - S.lstart[d]);
     if (g < cap) {
       keys_out[g] = k;
       vals_out[g] = v;
-      if (area_out) {  // tile-rectangle area of record v
+      if (area_out) {  // tile record and tile-rectangle area of record v
         const uint4 rc = rect[v];
         area_out[g] = ((rc.x >> 16) - (rc.x & 0xFFFFu) + 1) * ((rc.y >> 16) - (rc.y & 0xFFFFu) + 1);
+        rect_out[g] = rc;
       }
     }
   }
@@ -441,35 +485,60 @@ void scan_words(uint32_t *data, uint32_t len, uint32_t *part, hipStream_t st) {
 
 uint32_t rdx_chunk(uint32_t cap) { return cap >= kRdxBig ? kRdxNT * 32u : kRdxNT * 8u; }
 
+// Digit widths of a counting sort over `bits` key bits: 8-bit passes, except
+// that 17 to 20 bits take two passes of 9 or 10 bits rather than three.
+int sort_passes(int bits, int widths[4]) {
+  if (bits > 16 && bits <= 20) {
+    widths[0] = widths[1] = (bits + 1) / 2;
+    return 2;
+  }
+  const int passes = std::max(1, (bits + 7) / 8);
+  for (int p = 0; p < passes; ++p) widths[p] = 8;
+  return passes;
+}
+
+template <int IPL, int BITS>
+void count_pass(const Ws &ws, uint32_t nblk, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                uint32_t *vout, const uint32_t *count_dev, uint32_t cap, int shift, uint32_t *aout, uint4 *rout,
+                hipStream_t st) {
+  k_digit_hist<IPL, BITS><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, shift, ws.radix_hist);
+  scan_words(ws.radix_hist, (1u << BITS) * nblk, ws.scan_part, st);
+  k_digit_scatter<IPL, BITS><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, count_dev, cap, shift,
+                                                      ws.radix_hist, ws.rec_rect, aout, rout);
+}
+
 // Stable sort of `cap` items, of which *count_dev (all if NULL) are live, by
 // the low `bits` bits of their keys.  Input (k0, v0; v0 = NULL: values are
 // the indices); pass p writes (kb, vb) for even p and (ka, va) for odd p,
 // the last pass (out_k, out_v), which must not be its own input.  (ka, va)
 // may be the input itself.  With area_out the last pass also writes the
-// tile-rectangle areas of the (record) values.
+// tile-rectangle areas of the (record) values, and their tile records to
+// rect_out, in sorted order.
 void counting_sort(const Ws &ws, const uint32_t *count_dev, uint32_t cap, int bits, const uint32_t *k0,
                    const uint32_t *v0, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *out_k,
-                   uint32_t *out_v, uint32_t *area_out, hipStream_t st) {
+                   uint32_t *out_v, uint32_t *area_out, uint4 *rect_out, hipStream_t st) {
   const uint32_t chunk = rdx_chunk(cap);
   const uint32_t nblk = std::max<uint32_t>((cap + chunk - 1) / chunk, 1u);
-  const int passes = std::max(1, (bits + 7) / 8);
+  int widths[4];
+  const int passes = sort_passes(bits, widths);
   const uint32_t *kin = k0, *vin = v0;
+  int shift = 0;
   for (int p = 0; p < passes; ++p) {
     const bool last = p == passes - 1;
     uint32_t *kout = last ? out_k : (p % 2 == 0 ? kb : ka);
     uint32_t *vout = last ? out_v : (p % 2 == 0 ? vb : va);
     uint32_t *aout = last ? area_out : nullptr;
-    if (chunk == kRdxNT * 32u) {
-      k_digit_hist<32><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, 8 * p, ws.radix_hist);
-      scan_words(ws.radix_hist, 256u * nblk, ws.scan_part, st);
-      k_digit_scatter<32><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, count_dev, cap, 8 * p,
-                                                   ws.radix_hist, ws.rec_rect, aout);
-    } else {
-      k_digit_hist<8><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, count_dev, cap, 8 * p, ws.radix_hist);
-      scan_words(ws.radix_hist, 256u * nblk, ws.scan_part, st);
-      k_digit_scatter<8><<<nblk, kRdxNT, 0, st>>>(ws.scalars, kin, vin, kout, vout, count_dev, cap, 8 * p,
-                                                  ws.radix_hist, ws.rec_rect, aout);
+    uint4 *rout = last ? rect_out : nullptr;
+    const bool big = chunk == kRdxNT * 32u;
+    switch (widths[p] * 2 + (big ? 1 : 0)) {
+      case 16: count_pass<8, 8>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
+      case 17: count_pass<32, 8>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
+      case 18: count_pass<8, 9>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
+      case 19: count_pass<32, 9>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
+      case 20: count_pass<8, 10>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
+      default: count_pass<32, 10>(ws, nblk, kin, vin, kout, vout, count_dev, cap, shift, aout, rout, st); break;
     }
+    shift += widths[p];
     kin = kout;
     vin = vout;
   }
@@ -480,14 +549,16 @@ int bit_width(uint32_t x) { return x == 0 ? 0 : 32 - __builtin_clz(x); }
 }  // namespace
 
 // Records by depth bits (four passes): the last pass reads rec_tmp[2..3]
-// and writes the order to rec_tmp[0..1] (record indices in rec_tmp[1]) and
-// the records' tile-rectangle areas to rec_tmp[4].
+// and writes the order to rec_tmp[0..1] (record indices in rec_tmp[1]), the
+// records' tile-rectangle areas to rec_tmp[4] and their tile records to the
+// start of the backward's partials (free until the tile sort, 48 bytes per
+// record and more), so that the emission reads them in order.
 void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st) {
   if (sz.cap_rec == 0) return;
   uint32_t *q[5];
   for (int k = 0; k < 5; ++k) q[k] = ws.rec_tmp + (size_t)k * sz.cap_rec;
   counting_sort(ws, ws.scalars + kNumRecords, sz.cap_rec, 32, ws.rec_zbits, nullptr, q[0], q[1], q[2], q[3], q[0],
-                q[1], q[4], st);
+                q[1], q[4], reinterpret_cast<uint4 *>(ws.partials), st);
 }
 
 void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStream_t st) {
@@ -503,19 +574,22 @@ void launch_binning(const ViewInfo *views, const Ws &ws, const Sizes &sz, hipStr
   uint32_t *kb = reinterpret_cast<uint32_t *>(ws.partials), *vb = kb + sz.cap_pairs;
   const uint32_t waves = (sz.cap_rec + kWave - 1) / kWave;
   const uint32_t blocks = std::min<uint32_t>((waves + 3) / 4, 8192u);
-  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(ws, sz, perm, offs, ka, va);
+  // the tile records in depth order, written by the depth sort's last pass
+  const uint4 *srect = reinterpret_cast<const uint4 *>(ws.partials);
+  k_emit<<<std::max(blocks, 1u), 256, 0, st>>>(ws, sz, perm, srect, offs, ka, va);
   const int bits = std::max(1, bit_width(sz.t_tot - 1));
-  const int passes = (bits + 7) / 8;
+  int widths[4];
+  const int passes = sort_passes(bits, widths);
   // the last pass reads (kb, vb) when the pass count is even, else (ka, va)
   uint32_t *sorted_tiles = (passes % 2 == 1) ? kb : ka;
   counting_sort(ws, ws.scalars + kNumPairs, sz.cap_pairs, bits, ka, va, ka, va, kb, vb, sorted_tiles, ws.tile_recs,
-                nullptr, st);
+                nullptr, nullptr, st);
   const uint32_t bb = std::min<uint32_t>((sz.cap_pairs + 255) / 256, 16384u);
   k_tile_bounds<<<std::max(bb, 1u), 256, 0, st>>>(ws, sz, sorted_tiles);
   uint32_t *ok = ws.tile_tmp, *ov = ok + sz.t_tot, *ok2 = ov + sz.t_tot, *ov2 = ok2 + sz.t_tot;
   k_tile_classify<<<(sz.t_tot + 255) / 256, 256, 0, st>>>(ws, sz, ok, ov);
   // longest list first: one pass over the 8-bit length codes
-  counting_sort(ws, nullptr, sz.t_tot, 8, ok, ov, ok, ov, ok2, ov2, ok2, ws.tile_order, nullptr, st);
+  counting_sort(ws, nullptr, sz.t_tot, 8, ok, ov, ok, ov, ok2, ov2, ok2, ws.tile_order, nullptr, nullptr, st);
 }
 
 // Exclusive scan of the list lengths: the CSR offsets of the tile lists

@@ -54,7 +54,7 @@ struct Ws {
   uint32_t *rec_tmp;        // [5][cap_rec] depth sort of the records, pair offsets
   uint32_t *tile_order;     // [T_tot] tiles by decreasing list length
   uint32_t *tile_tmp;       // [4][T_tot] keys and values of the tile-order sort
-  uint32_t *radix_hist;     // [256][blocks] digit histograms of the counting passes
+  uint32_t *radix_hist;     // [radix][blocks] digit histograms of the counting passes (radix <= 1024)
   uint32_t *scan_part;      // chunk sums of the device-wide scans
   uint32_t *pairs_tmp;      // [2][cap_pairs] tile ids and records of the tile sort
   uint32_t *tile_recs;      // [cap_pairs] record list of every tile, in depth order

@@ -145,7 +145,7 @@ Layout make_layout(const Sizes &s) {
   // digits; the device-wide scans take 4096 words per chunk
   const size_t items = std::max<size_t>(std::max<size_t>(s.cap_pairs, s.cap_rec), s.t_tot);
   const size_t radix_blocks = std::max<size_t>((items + 2047) / 2048, 1);
-  const size_t scan_words = std::max<size_t>(std::max<size_t>(256 * radix_blocks, s.cap_rec), (size_t)s.t_tot + 1);
+  const size_t scan_words = std::max<size_t>(std::max<size_t>(1024 * radix_blocks, s.cap_rec), (size_t)s.t_tot + 1);
   put(L.scalars, kNumScalars * 4);
   put(L.queues, 2 * kQueueLanes * kQueueStride * 4);
   put(L.tile_count, (size_t)s.t_tot * 4);
@@ -163,7 +163,7 @@ Layout make_layout(const Sizes &s) {
   put(L.rec_tmp, (size_t)s.cap_rec * 20);
   put(L.tile_order, (size_t)s.t_tot * 4);
   put(L.tile_tmp, (size_t)s.t_tot * 16);
-  put(L.radix_hist, 256 * radix_blocks * 4);
+  put(L.radix_hist, 1024 * radix_blocks * 4);
   put(L.scan_part, (scan_words + 4095) / 4096 * 4);
   put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
   put(L.tile_recs, (size_t)s.cap_pairs * 4);

@@ -198,18 +198,28 @@ def test_graph_replays_match_eager(persistent):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("case", ["one_pass", "two_passes", "three_passes"])
+# (case, tile size, copies of the six 1600x900 cameras): the tile sort takes
+# 8-bit passes up to 2^16 tiles, two 9- or 10-bit passes up to 2^20 tiles and
+# 8-bit passes beyond.
+PASS_CASES = {
+    "one_8bit": (16, 0),        # 12 tiles, one camera
+    "two_8bit": (16, 1),        # 34,200 tiles
+    "two_9bit": (8, 1),         # 135,600 tiles
+    "two_10bit": (8, 2),        # 271,200 tiles
+    "three_8bit": (8, 8),       # 1,084,800 tiles
+}
+
+
+@pytest.mark.parametrize("case", list(PASS_CASES))
 def test_tile_sort_pass_counts_bit_exact(case):
-    """The tile sort takes one, two or three 8-bit counting passes by the
-    number of tiles in the batch (12, 34,200 and 271,200 tiles here)."""
-    if case == "one_pass":
+    """Tile lists bit-exact against the oracle at each digit plan of the tile
+    sort, and the image equal to the one binned at 32 px."""
+    ts, copies = PASS_CASES[case]
+    if copies == 0:
         scene_, cams = make_config(1)
-        ts = 16
     else:
         scene_, cams = make_config(3, scale=0.01)
-        ts = 16 if case == "two_passes" else 8
-        if case == "three_passes":
-            cams = cams + cams
+        cams = cams * copies
     rast, params, out = render_gpu(scene_, cams, ts=ts)
     log(f"{case}: {rast.required_capacity()[2]} tiles")
     keys, vals, csr = rast.debug_binning()
