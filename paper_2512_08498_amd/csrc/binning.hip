@@ -551,8 +551,8 @@ int bit_width(uint32_t x) { return x == 0 ? 0 : 32 - __builtin_clz(x); }
 // Records by depth bits (four passes): the last pass reads rec_tmp[2..3]
 // and writes the order to rec_tmp[0..1] (record indices in rec_tmp[1]), the
 // records' tile-rectangle areas to rec_tmp[4] and their tile records to the
-// start of the backward's partials (free until the tile sort, 48 bytes per
-// record and more), so that the emission reads them in order.
+// start of the backward's partials (free until the tile sort, at least 48
+// bytes per record), so that the emission reads them in order.
 void launch_depth_sort(const Ws &ws, const Sizes &sz, hipStream_t st) {
   if (sz.cap_rec == 0) return;
   uint32_t *q[5];

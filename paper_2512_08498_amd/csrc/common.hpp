@@ -58,7 +58,7 @@ struct Ws {
   uint32_t *scan_part;      // chunk sums of the device-wide scans
   uint32_t *pairs_tmp;      // [2][cap_pairs] tile ids and records of the tile sort
   uint32_t *tile_recs;      // [cap_pairs] record list of every tile, in depth order
-  float4 *partials;         // [cap_pairs][3] backward partial gradients per pair
+  float *partials;          // [cap_pairs][9] backward partial gradients per pair, 36 bytes each
   float4 *g2d;              // [cap_rec][3] per-record reduced gradients
   float *loss_partials;     // [kLossBlocks]
 };

@@ -29,6 +29,19 @@ namespace gsr {
 
 constexpr float kLn2 = 0x1.62e43p-1f;
 
+// A pair's nine partial gradients, packed at slot * 9 (36 bytes, so only
+// 4-byte aligned).
+__device__ __forceinline__ void store_partial(const Ws &ws, uint32_t slot, const float (&v)[9]) {
+  float *dst = ws.partials + (size_t)slot * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[k] = v[k];
+}
+
+__device__ __forceinline__ void store_zero_partial(const Ws &ws, uint32_t slot) {
+  const float z[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  store_partial(ws, slot, z);
+}
+
 // Barrier over the threads that share one tile's LDS: the workgroup, or a
 // single wave (whose LDS accesses are performed in order).
 template <bool WG>
@@ -126,14 +139,8 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
     }
     return ws.rec_pairoff[rec] + (ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
   };
-  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // entries no pixel reaches get zero gradients
-  for (uint32_t i = max_last + t; i < n; i += NT) {
-    const uint32_t slot = pair_slot(ws.tile_recs[start + i]);
-    ws.partials[(size_t)slot * 3 + 0] = zero4;
-    ws.partials[(size_t)slot * 3 + 1] = zero4;
-    ws.partials[(size_t)slot * 3 + 2] = zero4;
-  }
+  for (uint32_t i = max_last + t; i < n; i += NT) store_zero_partial(ws, pair_slot(ws.tile_recs[start + i]));
 
   // batches walk the list backwards; the next (earlier) batch is fetched
   // into registers while the current one is processed
@@ -173,9 +180,7 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       L.out[cs] = fslot;
       L.pos[cs] = lo + (uint32_t)t;
     } else if ((uint32_t)t < m) {
-      ws.partials[(size_t)fslot * 3 + 0] = zero4;
-      ws.partials[(size_t)fslot * 3 + 1] = zero4;
-      ws.partials[(size_t)fslot * 3 + 2] = zero4;
+      store_zero_partial(ws, fslot);
     }
     if (lo > 0) {
       const uint32_t lo2 = batch_lo(lo);
@@ -280,9 +285,9 @@ __device__ __forceinline__ void bwd_walk(const ViewInfo *__restrict__ views, con
       const uint32_t slot = L.out[e];
       const float qa2 = 2.0f * L.p1[e].z, qb = L.p1[e].w, qc2 = 2.0f * L.p2[e].x;
       const float d_offx = -qa2 * s9[0], d_offy = -fmaf(qa2 * qb, s9[0], qc2 * s9[1]);
-      ws.partials[(size_t)slot * 3 + 0] = make_float4(d_offx * kLn2, d_offy * kLn2, s9[2] * kLn2, qa2 * s9[3] * kLn2);
-      ws.partials[(size_t)slot * 3 + 1] = make_float4(s9[4] * kLn2, s9[5], s9[6], s9[7]);
-      ws.partials[(size_t)slot * 3 + 2] = make_float4(s9[8], 0.0f, 0.0f, 0.0f);
+      const float v[9] = {d_offx * kLn2, d_offy * kLn2, s9[2] * kLn2, qa2 * s9[3] * kLn2, s9[4] * kLn2,
+                          s9[5],          s9[6],          s9[7],          s9[8]};
+      store_partial(ws, slot, v);
     }
     hi = lo;
   }
@@ -364,11 +369,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) __attribute__((amdgpu_waves_per_eu
 // hold its wave for hundreds of dependent loads.
 constexpr uint32_t kBig = 16;
 
-__device__ __forceinline__ void add_partial(const float4 *__restrict__ src, float (&v)[9]) {
-  const float4 x = src[0], y = src[1], z = src[2];
-  v[0] += x.x; v[1] += x.y; v[2] += x.z; v[3] += x.w;
-  v[4] += y.x; v[5] += y.y; v[6] += y.z; v[7] += y.w;
-  v[8] += z.x;
+__device__ __forceinline__ void add_partial(const float *__restrict__ src, float (&v)[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] += src[k];
 }
 
 // step (optional): the Adam step counter, incremented here (before the
@@ -399,10 +402,10 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
       for (int k = 0; k < 9; ++k) a[k] = b[k] = 0.0f;
       uint32_t k = 0;
       for (; k + 1 < cnt; k += 2) {
-        add_partial(ws.partials + (size_t)(p0 + k) * 3, a);
-        add_partial(ws.partials + (size_t)(p0 + k + 1) * 3, b);
+        add_partial(ws.partials + (size_t)(p0 + k) * 9, a);
+        add_partial(ws.partials + (size_t)(p0 + k + 1) * 9, b);
       }
-      if (k < cnt) add_partial(ws.partials + (size_t)(p0 + k) * 3, a);
+      if (k < cnt) add_partial(ws.partials + (size_t)(p0 + k) * 9, a);
 #pragma unroll
       for (int c = 0; c < 9; ++c) a[c] += b[c];
       ws.g2d[(size_t)r * 3 + 0] = make_float4(a[0], a[1], a[2], a[3]);
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
       float v[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-      for (uint32_t k = lane; k < bc; k += kWave) add_partial(ws.partials + (size_t)(bp + k) * 3, v);
+      for (uint32_t k = lane; k < bc; k += kWave) add_partial(ws.partials + (size_t)(bp + k) * 9, v);
       const float sum = wave_sum9_packed(v);  // value l in lane l < 8, value 8 in lane 32
       float *dst = reinterpret_cast<float *>(ws.g2d + (size_t)(wbase + l) * 3);
       if (lane < 8) dst[lane] = sum;

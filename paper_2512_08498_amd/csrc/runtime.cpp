@@ -128,7 +128,7 @@ Ws make_ws(const gsr_ctx *c, void *base) {
   w.scan_part = reinterpret_cast<uint32_t *>(b + L.scan_part);
   w.pairs_tmp = reinterpret_cast<uint32_t *>(b + L.pairs_tmp);
   w.tile_recs = reinterpret_cast<uint32_t *>(b + L.tile_recs);
-  w.partials = reinterpret_cast<float4 *>(b + L.partials);
+  w.partials = reinterpret_cast<float *>(b + L.partials);
   w.g2d = reinterpret_cast<float4 *>(b + L.g2d);
   w.loss_partials = c->loss_partials;
   return w;
@@ -167,8 +167,9 @@ Layout make_layout(const Sizes &s) {
   put(L.scan_part, (scan_words + 4095) / 4096 * 4);
   put(L.pairs_tmp, (size_t)s.cap_pairs * 8);
   put(L.tile_recs, (size_t)s.cap_pairs * 4);
-  // per-pair partials; the pose gradients reuse them per record afterwards
-  put(L.partials, (size_t)std::max(s.cap_pairs, s.cap_rec) * 48);
+  // per-pair partials (36 bytes); the pose gradients reuse them afterwards
+  // as 48 bytes per record
+  put(L.partials, std::max((size_t)s.cap_pairs * 36, (size_t)s.cap_rec * 48));
   put(L.g2d, (size_t)s.cap_rec * 48);
   put(L.cam_part, (size_t)cam_chunks(s.cap_rec) * (size_t)s.n_views * 48);
   put(L.loss_part, (size_t)raster_fwd_grid(s) * 4);
@@ -459,7 +460,7 @@ gsr_status gsr_render_backward(gsr_ctx *c, const gsr_gaussians *g, const gsr_cam
   if (c->n > 0 && any_null(gr)) return fail(c, GSR_ERR_INVALID_ARG, "a gradient pointer is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
-  float4 *cam_rec = grads->camera ? ws.partials : nullptr;
+  float4 *cam_rec = grads->camera ? reinterpret_cast<float4 *>(ws.partials) : nullptr;
   {
     StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
     launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
@@ -541,7 +542,7 @@ gsr_status gsr_render_backward_adam(gsr_ctx *c, const gsr_gaussians *g, const gs
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Ws ws = make_ws(c, ws_base);
-  float4 *cam_rec = grads_out && grads_out->camera ? ws.partials : nullptr;
+  float4 *cam_rec = grads_out && grads_out->camera ? reinterpret_cast<float4 *>(ws.partials) : nullptr;
   {
     StageTimer tm(c, GSR_STAGE_RASTER_BWD, s);
     launch_raster_bwd(c->views_d, ws, c->sz, fwd->t_final, fwd->last_pos, dL_dimage, s);
