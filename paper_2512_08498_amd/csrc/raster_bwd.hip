@@ -400,7 +400,22 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(Ws ws, int32_t *step) {
       float a[9], b[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) a[k] = b[k] = 0.0f;
+      // even pairs into a, odd ones into b, in order; four pairs' loads are
+      // issued before their sums
       uint32_t k = 0;
+      for (; k + 3 < cnt; k += 4) {
+        const float *src = ws.partials + (size_t)(p0 + k) * 9;
+        float x[36];
+#pragma unroll
+        for (int c = 0; c < 36; ++c) x[c] = src[c];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          a[c] += x[c];
+          b[c] += x[9 + c];
+          a[c] += x[18 + c];
+          b[c] += x[27 + c];
+        }
+      }
       for (; k + 1 < cnt; k += 2) {
         add_partial(ws.partials + (size_t)(p0 + k) * 9, a);
         add_partial(ws.partials + (size_t)(p0 + k + 1) * 9, b);
