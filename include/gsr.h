@@ -219,7 +219,9 @@ gsr_status gsr_adam_step(gsr_ctx *ctx, const gsr_grads *params, const gsr_grads 
  * as gsr_render_backward followed by gsr_adam_step with grads zeroed first.
  * grads_out, if given, receives the gradients too: its five Gaussian
  * pointers all set or all NULL, its camera pointer as in gsr_grads (the
- * pose gradient for a separate camera update).                            */
+ * pose gradient for a separate camera update).  params may be the arrays
+ * of g (updated in place) or other arrays; params, m, v and grads_out must
+ * not overlap one another.                                                 */
 gsr_status gsr_render_backward_adam(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                                     int32_t n_views, void *workspace, size_t workspace_bytes,
                                     const gsr_fwd_out *fwd, const float *dL_dimage,

@@ -202,26 +202,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float bc1 = 1.0f, bc2 = 1.0f;
   if (ADAM) bias_corrections(adam, bc1, bc2);
   // Gradients of a group of N parameters (pointer offsets off[i] from the
-  // group's arrays) whose current values pv the thread already holds:
-  // written out, or applied by Adam with all loads of the group issued
-  // before any store, so the memory latency is paid once per group rather
-  // than once per parameter.
-  auto emit_group = [&](auto tag, float *p, float *m, float *v, float *gout, const int64_t(&off)[decltype(tag)::N],
-                        const float(&pv)[decltype(tag)::N], const float(&gv)[decltype(tag)::N],
-                        const float(&lr)[decltype(tag)::N]) {
-    constexpr int N = decltype(tag)::N;
-    if (!ADAM) {
+  // group's arrays) whose current values pv the thread already holds.
+  // Without Adam they are written out (or added).  With Adam a group's loads
+  // (the moments, and the values unless the parameters are the forward's own
+  // arrays) are issued apart from its update and stores, so the loads of
+  // several groups are in flight before any of their stores: the three
+  // view-independent groups together, and each SH group (then the mean)
+  // while the group before it is stored.  Parameters, moments and gradient
+  // outputs are distinct arrays, so no store feeds a later load.
+  auto write_grads = [&](auto tag, float *gout, const int64_t(&off)[decltype(tag)::N],
+                         const float(&gv)[decltype(tag)::N]) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) gout[off[i]] = accumulate ? gout[off[i]] + gv[i] : gv[i];
-      return;
-    }
-    float pp[N], mm[N], vv[N];
+    for (int i = 0; i < decltype(tag)::N; ++i) gout[off[i]] = accumulate ? gout[off[i]] + gv[i] : gv[i];
+  };
+  auto adam_load = [&](auto tag, const float *p, const float *m, const float *v,
+                       const int64_t(&off)[decltype(tag)::N], const float(&pv)[decltype(tag)::N],
+                       float(&pp)[decltype(tag)::N], float(&mm)[decltype(tag)::N], float(&vv)[decltype(tag)::N]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < decltype(tag)::N; ++i) {
       pp[i] = adam.p_is_g ? pv[i] : p[off[i]];
       mm[i] = m[off[i]];
       vv[i] = v[off[i]];
     }
+  };
+  auto adam_store = [&](auto tag, float *p, float *m, float *v, float *gout, const int64_t(&off)[decltype(tag)::N],
+                        float(&pp)[decltype(tag)::N], float(&mm)[decltype(tag)::N], float(&vv)[decltype(tag)::N],
+                        const float(&gv)[decltype(tag)::N], const float(&lr)[decltype(tag)::N]) {
+    constexpr int N = decltype(tag)::N;
 #pragma unroll
     for (int i = 0; i < N; ++i) adam_update(pp[i], mm[i], vv[i], gv[i], lr[i], adam.beta1, adam.beta2, adam.eps, bc1, bc2);
 #pragma unroll
@@ -239,17 +246,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float lr1[3] = {adam.lr[1], adam.lr[1], adam.lr[1]};
     const float lr2[4] = {adam.lr[2], adam.lr[2], adam.lr[2], adam.lr[2]}, lr3[1] = {adam.lr[3]};
     const float gth[1] = {d_theta}, th[1] = {theta};
-    emit_group(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, o3, l3, d_l, lr1);
-    emit_group(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, o4, q4, d_q, lr2);
-    emit_group(GroupN<1>{}, adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, grads.opacity_logit,
-               o1, th, gth, lr3);
+    if (!ADAM) {
+      write_grads(GroupN<3>{}, grads.log_scale, o3, d_l);
+      write_grads(GroupN<4>{}, grads.quat, o4, d_q);
+      write_grads(GroupN<1>{}, grads.opacity_logit, o1, gth);
+    } else {
+      float ps[3], ms[3], vs[3], pq[4], mq[4], vq[4], po[1], mo[1], vo[1];
+      adam_load(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, o3, l3, ps, ms, vs);
+      adam_load(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, o4, q4, pq, mq, vq);
+      adam_load(GroupN<1>{}, adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit, o1, th, po, mo, vo);
+      adam_store(GroupN<3>{}, adam.p.log_scale, adam.m.log_scale, adam.v.log_scale, grads.log_scale, o3, ps, ms, vs,
+                 d_l, lr1);
+      adam_store(GroupN<4>{}, adam.p.quat, adam.m.quat, adam.v.quat, grads.quat, o4, pq, mq, vq, d_q, lr2);
+      adam_store(GroupN<1>{}, adam.p.opacity_logit, adam.m.opacity_logit, adam.v.opacity_logit,
+                 grads.opacity_logit, o1, po, mo, vo, gth, lr3);
+    }
   }
 
   // pass 2: the SH coefficients, loaded once (the values the Adam update
   // starts from too), and one walk over the records for the colour's
   // dependence on the viewing direction and the coefficients' gradient sums;
   // those sums sit in this thread's column of LDS (registers would spill),
-  // then the updates go in groups of two coefficients (six parameters)
+  // then the updates go in groups of two coefficients (six parameters; three
+  // at degree 2)
   float shv[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -288,11 +307,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       d_dir[2] += (gd[2] - dot * d[2]) * inv;
     }
   }
-  constexpr int KC = K < 2 ? K : 2;
-#pragma unroll
-  for (int kc = 0; kc < K; kc += KC) {
-    int64_t off[3 * KC];
-    float pv[3 * KC], gv[3 * KC], lr[3 * KC];
+  // coefficients per group: a divisor of K (degree 2 has nine), so no group
+  // runs past the last coefficient
+  constexpr int KC = K % 2 == 0 ? 2 : (K % 3 == 0 ? 3 : 1);
+  constexpr int NG = 3 * KC;
+  // offsets, current values and learning rates of the SH group at kc
+  auto sh_group = [&](int kc, int64_t(&off)[NG], float(&pv)[NG], float(&lr)[NG]) {
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
@@ -300,17 +320,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const int k = kc + kk;
         off[3 * kk + ch] = ((int64_t)k * 3 + ch) * n + g;
         pv[3 * kk + ch] = shv[k][ch];
-        gv[3 * kk + ch] = a_lds[3 * k + ch][tc];
         lr[3 * kk + ch] = k == 0 ? adam.lr[4] : adam.lr[5];
       }
-    emit_group(GroupN<3 * KC>{}, adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, off, pv, gv, lr);
-  }
-  // the mean's update, now that the direction term is in
-  {
-    const float dm[3] = {d_mean[0] + d_dir[0], d_mean[1] + d_dir[1], d_mean[2] + d_dir[2]};
-    const int64_t o3[3] = {g, n + g, 2 * n + g};
-    const float lr0[3] = {adam.lr[0], adam.lr[0], adam.lr[0]};
-    emit_group(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, o3, m3, dm, lr0);
+  };
+  auto sh_grads = [&](int kc, float(&gv)[NG]) {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gv[3 * kk + ch] = a_lds[3 * (kc + kk) + ch][tc];
+  };
+  const float dm[3] = {d_mean[0] + d_dir[0], d_mean[1] + d_dir[1], d_mean[2] + d_dir[2]};
+  const int64_t o3[3] = {g, n + g, 2 * n + g};
+  const float lr0[3] = {adam.lr[0], adam.lr[0], adam.lr[0]};
+  if (!ADAM) {
+#pragma unroll
+    for (int kc = 0; kc < K; kc += KC) {
+      int64_t off[NG];
+      float pv[NG], gv[NG], lr[NG];
+      sh_group(kc, off, pv, lr);
+      sh_grads(kc, gv);
+      write_grads(GroupN<NG>{}, grads.sh, off, gv);
+    }
+    // the mean, now that the direction term is in
+    write_grads(GroupN<3>{}, grads.mean, o3, dm);
+  } else {
+    // only the loaded values are carried from one group to the next; the
+    // offsets and rates are recomputed
+    float np[NG], nm[NG], nv[NG];
+    {
+      int64_t off[NG];
+      float pv[NG], lr[NG];
+      sh_group(0, off, pv, lr);
+      adam_load(GroupN<NG>{}, adam.p.sh, adam.m.sh, adam.v.sh, off, pv, np, nm, nv);
+    }
+    float pmn[3], mmn[3], vmn[3];
+#pragma unroll
+    for (int kc = 0; kc < K; kc += KC) {
+      float pp[NG], mm[NG], vv[NG];
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        pp[i] = np[i];
+        mm[i] = nm[i];
+        vv[i] = nv[i];
+      }
+      if (kc + KC < K) {
+        int64_t off[NG];
+        float pv[NG], lr[NG];
+        sh_group(kc + KC, off, pv, lr);
+        adam_load(GroupN<NG>{}, adam.p.sh, adam.m.sh, adam.v.sh, off, pv, np, nm, nv);
+      } else {
+        adam_load(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, o3, m3, pmn, mmn, vmn);
+      }
+      int64_t off[NG];
+      float pv[NG], lr[NG], gv[NG];
+      sh_group(kc, off, pv, lr);
+      sh_grads(kc, gv);
+      adam_store(GroupN<NG>{}, adam.p.sh, adam.m.sh, adam.v.sh, grads.sh, off, pp, mm, vv, gv, lr);
+    }
+    // the mean, now that the direction term is in
+    adam_store(GroupN<3>{}, adam.p.mean, adam.m.mean, adam.v.mean, grads.mean, o3, pmn, mmn, vmn, dm, lr0);
   }
 }
 

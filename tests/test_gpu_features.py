@@ -71,8 +71,12 @@ def test_adam_matches_oracle_over_steps(cfg1):
         assert np.abs(got - p[k]).max() <= 1e-5 * step_scale + 1e-6 * np.abs(p[k]).max(), k
 
 
-def test_fused_backward_adam_equals_backward_then_adam():
-    scene_, cams = mini_rig()
+@pytest.mark.parametrize("degree", [3, 2, 1, 0])
+def test_fused_backward_adam_equals_backward_then_adam(degree):
+    """The fused step against the backward followed by the separate Adam
+    kernel, at every SH degree (the fused kernel updates the coefficients in
+    groups whose loads overlap the previous group's stores)."""
+    scene_, cams = mini_rig(degree=degree)
     rng = np.random.default_rng(5)
     rast, params, out = render_gpu(scene_, cams)
     dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-4).cuda()
@@ -91,12 +95,13 @@ def test_fused_backward_adam_equals_backward_then_adam():
         assert torch.equal(opt1.m[k], opt2.m[k]), k
 
 
-def test_fused_adam_into_separate_parameter_arrays():
+@pytest.mark.parametrize("degree", [3, 2])
+def test_fused_adam_into_separate_parameter_arrays(degree):
     """The fused step may update parameter arrays other than the rendered
     Gaussians' own (holding the same values): the result equals the
     in-place update bit for bit, so the kernel's reuse of the values it has
     already loaded is only taken when the arrays are the same."""
-    scene_, cams = mini_rig()
+    scene_, cams = mini_rig(degree=degree)
     rng = np.random.default_rng(6)
     rast, params, out = render_gpu(scene_, cams)
     dl = torch.from_numpy(rng.standard_normal(3 * rast.total_px).astype(np.float32) * 1e-4).cuda()

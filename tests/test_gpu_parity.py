@@ -108,6 +108,31 @@ def test_backward_posed_two_views_sh3():
     _check_backward(scene, cams, targets)
 
 
+@pytest.mark.parametrize("degree", [0, 1, 2])
+def test_forward_and_backward_other_sh_degrees(degree):
+    """The mini rig at SH degrees 0, 1 and 2 (degree 3 above): image and
+    gradients against the oracle.  Every gradient array sits at the front of
+    a buffer twice its size filled with a sentinel, which must survive: the
+    per-Gaussian kernel updates the SH coefficients in groups, and degree 2
+    has an odd count (nine) of them."""
+    scene, cams = mini_rig(degree=degree)
+    log(f"mini rig, SH degree {degree}")
+    oracle = render(scene, cams)
+    rast, params, out = _check_forward(scene, cams, 16, oracle=oracle)
+    rng = np.random.default_rng(30 + degree)
+    targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in cams]
+    cots = _masked_cotangent(oracle, targets)
+    dl = torch.from_numpy(np.concatenate([c.astype(np.float32).reshape(-1) for c in cots])).cuda()
+    sentinel = -12345.5
+    bufs = {k: torch.full((2 * v.numel(),), sentinel, dtype=torch.float32, device="cuda") for k, v in params.items()}
+    grads = {k: bufs[k][:v.numel()].view(v.shape) for k, v in params.items()}
+    rast.backward(params, out, dl, grads=grads)
+    torch.cuda.synchronize()
+    for k, b in bufs.items():
+        assert bool((b[params[k].numel():] == sentinel).all()), k
+    _compare_grads(grads_to_host(grads), grad64(scene, cams, cots))
+
+
 @pytest.mark.parametrize("ts,long_list", [(16, 1024), (16, 0), (8, 1024), (32, 1024)])
 def test_needles_forward_and_backward(ts, long_list):
     """Elongated footprints near the opacity threshold: the backward drops,
