@@ -314,7 +314,7 @@ def window_leg(args, dev, replayable, timed):
     r.forward(params)
     rec, pairs, _ = r.required_capacity()
     r._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
-    tuning = r.autotune(params, repeats=3)
+    tuning = r.autotune(params, repeats=5)
     r.forward(params)
     rec, pairs, _ = r.required_capacity()
     r._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
@@ -353,6 +353,9 @@ def main():
     ap.add_argument("--tile-size", type=int, default=0, help="8, 16 or 32; 0 (default) = autotune on the workload")
     ap.add_argument("--persistent", type=int, default=0, choices=(0, 1),
                     help="with --tile-size: 1 = persistent compositing launches (the autotuner chooses otherwise)")
+    ap.add_argument("--long-list", type=int, default=1024,
+                    help="with --tile-size 16: lists this long are walked by a whole workgroup (the autotuner "
+                         "chooses otherwise)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
@@ -405,7 +408,8 @@ def main():
 
     cap_rec = max(len(cams) * scene.n // 4, 65536)
     rast = Rasterizer(cams, scene.n, scene.sh_degree, tile_size=args.tile_size or 16, device=dev,
-                      capacity_records=cap_rec, capacity_pairs=4 * cap_rec, persistent=bool(args.persistent))
+                      capacity_records=cap_rec, capacity_pairs=4 * cap_rec, persistent=bool(args.persistent),
+                      long_list=args.long_list)
     out = rast.forward(params)  # re-plans on capacity overflow
     rec, pairs, tiles = rast.required_capacity()
     # headroom for the scene to move during training
@@ -413,7 +417,7 @@ def main():
     tuning = None
     if args.tile_size == 0:
         t_tune = time.perf_counter()
-        tuning = rast.autotune(params, repeats=3)
+        tuning = rast.autotune(params, repeats=5)
         out = rast.forward(params)
         rec, pairs, tiles = rast.required_capacity()
         rast._plan(int(rec * 1.5) + 4096, int(pairs * 1.5) + 65536)
