@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *__restrict__ da
 }
 
 // 2b. Stable scatter of one block's chunk by digit.  Wave w owns the w-th
-// quarter of the chunk and loads all of it first (32 items per lane).  It
+// quarter of the chunk and loads all of it first (IPL items per lane).  It
 // ranks its items by digit round by round (64 items, in order) with ballot
 // matches and its own running digit counts in LDS, so no workgroup barrier
 // is needed per round.  The block then places its items in LDS in local
