@@ -51,10 +51,10 @@ __device__ __forceinline__ uint32_t n_items(const uint32_t *count_dev, uint32_t 
 
 // Emission: each wave takes 64 consecutive records of the depth order (their
 // indices perm[i] and tile records srect[i] are read in order); their pairs
-// form one contiguous range (offs[i] is the first pair of sorted record i).  A record of at most kEmitSmall pairs is written by its own lane,
-// stepping through its tile rectangle; the lanes' stores fall into that one
-// range.  Bigger footprints are written by the
-// whole wave, 64 pairs per step.
+// form one contiguous range (offs[i] is the first pair of sorted record i).
+// A record of at most kEmitSmall pairs is written by its own lane, stepping
+// through its tile rectangle; the lanes' stores fall into that one range.
+// Bigger footprints are written by the whole wave, 64 pairs per step.
 constexpr uint32_t kEmitSmall = 8;
 
 __global__ __launch_bounds__(256) void k_emit(Ws ws, Sizes sz,
@@ -360,13 +360,13 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
   {
     // the thread's DPT consecutive digits: local starts in digit order, then
     // per digit in wave order
-    uint32_t c[DPT][NW], tot = 0;
+    uint32_t cnt[DPT][NW], tot = 0;
 #pragma unroll
     for (int e = 0; e < DPT; ++e)
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
-        c[e][k] = S.wcnt[k][t * DPT + (uint32_t)e];
-        tot += c[e][k];
+        cnt[e][k] = S.wcnt[k][t * DPT + (uint32_t)e];
+        tot += cnt[e][k];
       }
     uint32_t total;
     uint32_t run = block_excl_scan<kRdxNT>(tot, S.scan, total);
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kRdxNT) void k_digit_scatter(const uint32_t *__rest
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
         S.wcnt[k][d] = run;
-        run += c[e][k];
+        run += cnt[e][k];
       }
     }
   }
